@@ -1,0 +1,247 @@
+/*
+ * kt -- ML-pruned, per-shape-selected GEMM kernels for AMD MI355X (gfx950).
+ *
+ * C ABI of libkt.so.  Implements the method of J. Lawson, "Performance
+ * portability through machine learning guided kernel selection in SYCL
+ * libraries" (arXiv 2008.13145): a parameterized tiled matrix multiply
+ * (section 3), an exhaustive benchmark of its configuration space
+ * (sections 3 and 3.1), normalization of the timings (section 3.4), k-means
+ * pruning to k deployable kernels (sections 4.1-4.2), a decision-tree
+ * selector trained on the benchmark labels (section 5.1) and its evaluation
+ * against exhaustive search (section 4.3).
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ * - Matrices are row-major.  op(A) is M x K: stored M x K (lda >= K) when
+ *   transA == 0, stored K x M (lda >= M) when transA == 1.  op(B) is K x N:
+ *   stored K x N (ldb >= N) when transB == 0, N x K (ldb >= K) when 1.
+ *   C is M x N (ldc >= N).  Batch item b starts at ptr + b * stride.
+ * - Device pointers are owned by the caller and must stay valid until the
+ *   work queued on `stream` completes.  Host pointers are read or written
+ *   before the call returns.  The library allocates device memory only
+ *   where an entry point says so.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * - Every function returns a kt_status and never throws or aborts.  On
+ *   failure kt_last_error(handle) holds a message.  Asynchronous kernel
+ *   faults surface at the next synchronizing call.
+ * - A handle is not thread-safe; use one per thread.
+ */
+#ifndef KT_H
+#define KT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KT_OK = 0,
+  KT_EINVAL = -1,        /* bad argument (negative size, short leading dimension, ...) */
+  KT_EUNSUPPORTED = -2,  /* dtype / configuration / layout not compiled into this build */
+  KT_EHIP = -3,          /* a HIP runtime call failed; message has hipGetErrorString text */
+  KT_ENOTFITTED = -4,    /* selection requested before a selector was fitted or loaded */
+  KT_EWORKSPACE = -5,    /* workspace missing or smaller than the size query returned */
+  KT_EIO = -6            /* file could not be read / written, or is malformed */
+} kt_status;
+
+typedef enum { KT_F32 = 0, KT_BF16 = 1, KT_FP8E4M3 = 2 } kt_dtype;
+
+/* Normalizations of section 3.4 (integer Q16 reading, 65535 = 1.0). */
+typedef enum {
+  KT_NORM_RELATIVE = 0,  /* t_best / t */
+  KT_NORM_RAWCUT = 1,    /* relative, values below 0.9 set to 0 */
+  KT_NORM_STDCUT = 2,    /* raw cutoff, then [0.9, 1] rescaled onto [0, 1] */
+  KT_NORM_SIGMOID = 3    /* 1 / (1 + exp(50 (0.85 - x))) of the relative value */
+} kt_norm;
+
+/* Selectors: decision trees A/B/C of section 5.1, the MLP cost model, or
+ * exhaustive timing of every compiled configuration (cached per shape). */
+typedef enum {
+  KT_SEL_DT_A = 0,       /* no depth limit, min 1 sample per leaf */
+  KT_SEL_DT_B = 1,       /* depth <= 6, min 3 samples per leaf */
+  KT_SEL_DT_C = 2,       /* depth <= 3, min 4 samples per leaf */
+  KT_SEL_MLP = 3,
+  KT_SEL_EXHAUSTIVE = 4
+} kt_selector;
+
+typedef struct {
+  int64_t M, N, K, batch;
+  int32_t transA, transB;
+} kt_shape;
+
+/* One tile configuration (the layout comes from the shape).
+ * bm x bn: work-group output tile; t: per-lane thread tile, so each wave
+ * owns an (8t) x (8t) block and each lane t*t accumulators; bk: K depth of
+ * one LDS stage. */
+typedef struct {
+  int32_t bm, bn, t, bk;
+  int32_t dtype; /* kt_dtype */
+} kt_config;
+
+typedef struct kt_ctx* kt_handle;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Create a handle.  device >= 0 binds the handle to that HIP device (it
+ * becomes current on the calling thread).  device == -1 gives a host-only
+ * handle: configuration tables, selector fitting for decision trees,
+ * selection, save and load work; every entry point that launches GPU work
+ * returns KT_EINVAL. */
+kt_status kt_create(kt_handle* out, int device);
+kt_status kt_destroy(kt_handle h);
+/* Message of the last failed call on this handle ("" if none). Valid until the
+ * next call on the handle.  Also works with h == NULL (errors of kt_create). */
+const char* kt_last_error(kt_handle h);
+/* Semantic version of the ABI, e.g. 100 for 0.1.0. */
+int32_t kt_abi_version(void);
+
+/* ------------------------------------------------------ configuration space */
+
+/* Number of tile configurations compiled for a dtype (per layout).
+ * For KT_F32 the full space of section 3's kernel re-designed for MFMA:
+ * bm, bn in {8,16,32,64,128}, t in {1,2,4,8}, bk in {8,16,32,64}, with bm and bn
+ * multiples of 8t and 1..16 waves per work-group: 164 configurations. */
+kt_status kt_num_configs(kt_handle h, kt_dtype dtype, int32_t* n);
+/* Configuration `id` (0 <= id < n) of a dtype.  KT_EINVAL if out of range. */
+kt_status kt_get_config(kt_handle h, kt_dtype dtype, int32_t id, kt_config* out);
+/* 1 if configuration `id` is compiled for the (transA, transB) layout. */
+kt_status kt_config_compiled(kt_handle h, kt_dtype dtype, int32_t id, int32_t transA,
+                             int32_t transB, int32_t* compiled);
+
+/* ------------------------------------------------------------------- GEMM */
+
+/* C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]   (section 3).
+ * in_dtype selects the element type of A and B (FP32, BF16 stored as uint16
+ * bit patterns, or FP8 e4m3 codes); C is always FP32.  FP8 multiplies the
+ * product by alpha / (scaleA[0] * scaleB[0]) where scaleA/scaleB are device
+ * pointers to the per-tensor quantization scales (NULL for other dtypes).
+ * config_id >= 0 forces that configuration; -1 asks the fitted selector.
+ * With beta == 0, C is never read (NaN in C does not propagate).  M, N or
+ * batch == 0 is a no-op; K == 0 gives C = beta * C.  Unaligned pointers or
+ * leading dimensions take a scalar-load path; they are never an error. */
+kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha,
+                  const void* A, int64_t lda, int64_t strideA,
+                  const void* B, int64_t ldb, int64_t strideB,
+                  float beta, float* C, int64_t ldc, int64_t strideC,
+                  const float* scaleA, const float* scaleB,
+                  int32_t config_id, void* stream);
+
+/* Fill dst[i] (device, n floats) with the seeded operand stream
+ * x(seed, offset + i) = (splitmix64(seed XOR (offset + i)) >> 40) * 2^-23 - 1,
+ * values in [-1, 1) exact in FP32. */
+kt_status kt_fill_uniform(kt_handle h, float* dst, int64_t n, uint64_t seed, int64_t offset,
+                          void* stream);
+
+/* ------------------------------------------------------------------ sweep */
+
+typedef struct {
+  int32_t warmup;       /* untimed launches before timing (>= 0), default 1 */
+  float target_ms;      /* timed reps = clamp(ceil(target_ms / t_first), min_reps, max_reps) */
+  int32_t min_reps, max_reps;
+  float cut_factor;     /* if the first launch is slower than cut_factor x the row's best so
+                           far, record it and skip the timed reps (0 disables) */
+  float pause_ms;       /* host sleep between rows, to limit heating */
+  uint64_t seed;        /* operand seed base: A, B (and C if beta != 0) are filled per row */
+  float alpha, beta;
+} kt_sweep_opts;
+
+/* Device workspace needed to sweep these shapes (operands of the largest
+ * shape, 256-byte aligned). */
+kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_dtype dtype,
+                                   size_t* bytes);
+/* Time every (shape, configuration) pair (sections 3 and 3.1): for each shape
+ * the operands are filled in the workspace, then each configuration is
+ * launched `warmup` times and timed with HIP events over its reps; the mean
+ * nanoseconds per launch go to time_ns[shape * n_configs + c] (host, int64).
+ * config_ids (host) selects configurations (NULL = all of the dtype, in id
+ * order).  Entries already >= 0 in time_ns are kept (resume).  The call
+ * synchronizes `stream`. */
+kt_status kt_sweep(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n_shapes,
+                   const int32_t* config_ids, int32_t n_configs, const kt_sweep_opts* opts,
+                   void* workspace, size_t ws_bytes, void* stream, int64_t* time_ns);
+
+/* ---------------------------------------------------------- normalization */
+
+/* Normalize a device int64 time table [n_rows][n_configs] into device uint16
+ * Q16 values (section 3.4): q = round_half_up(65535 * t_best / t) with t_best
+ * the row's smallest positive time (t <= 0 gives 0), then the chosen variant.
+ * Runs on `stream`, asynchronously. */
+kt_status kt_normalize(kt_handle h, const int64_t* d_time, int32_t n_rows, int32_t n_configs,
+                       kt_norm norm, uint16_t* d_out, void* stream);
+
+/* ---------------------------------------------------------------- pruning */
+
+/* Workspace bytes for kt_prune. */
+kt_status kt_prune_workspace_bytes(int32_t n_rows, int32_t n_configs, int32_t k, int32_t n_init,
+                                   size_t* bytes);
+/* Choose k configurations by k-means over the normalized rows (sections 4.1
+ * and 4.2), on the GPU.  time_ns is a host table [n_rows][n_configs].
+ * k-means++ initialisation from a SplitMix64 stream seeded with seed + r for
+ * restart r, integer Lloyd iterations (exact int64 distances and sums,
+ * rounded-mean centroids), n_init restarts (lowest inertia wins, lowest r on
+ * ties), at most max_iter updates each.  Centroid j yields its best
+ * configuration not already chosen.  Outputs (host): chosen[k] column
+ * indices in cluster order, *inertia_out, and optionally labels[n_rows] and
+ * centroids[k * n_configs] (NULL to skip).  Synchronizes `stream`. */
+kt_status kt_prune(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                   int32_t k, kt_norm norm, uint64_t seed, int32_t n_init, int32_t max_iter,
+                   void* workspace, size_t ws_bytes, void* stream,
+                   int32_t* chosen, int64_t* inertia_out, int32_t* labels, int64_t* centroids);
+
+/* Top-N baseline of section 4.2: the k configurations that are best (largest
+ * normalized value, lowest index on ties) for the most rows, ties in the
+ * count to the lower index.  Host tables in and out. */
+kt_status kt_prune_topn(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                        int32_t k, int32_t* chosen);
+
+/* ------------------------------------------------------------- selection */
+
+typedef struct {
+  int32_t steps;          /* full-batch Adam steps (default 3000) */
+  float lr;               /* default 1e-3 */
+  const float* init;      /* host, optional: W1 (64x6), b1, W2 (64x64), b2, W3 (k x 64), b3
+                             packed in that order, row-major [out][in]; NULL = He-uniform
+                             from SplitMix64(seed) */
+  uint64_t seed;
+} kt_mlp_opts;
+
+/* Fit the runtime selector on n_rows problems (section 5.1).  shapes and
+ * time_ns are host arrays; chosen[k] are the deployed configuration ids.
+ * Each row is labelled with the fastest chosen configuration (lowest
+ * position on equal times).  Decision trees are fitted on the host (integer
+ * Gini CART on the raw features M, N, K, batch, transA, transB; split
+ * thresholds floor(sqrt(a*b)) between consecutive values; x <= t goes left).
+ * KT_SEL_MLP trains the cost model on the GPU (needs a device handle and a
+ * workspace of kt_mlp_workspace_bytes).  KT_SEL_EXHAUSTIVE needs no data. */
+kt_status kt_fit_selector(kt_handle h, kt_selector sel, const kt_shape* shapes,
+                          const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                          const int32_t* chosen, int32_t k, const kt_mlp_opts* mlp,
+                          void* workspace, size_t ws_bytes, void* stream);
+
+/* Configuration id for a shape (host).  KT_ENOTFITTED before a fit or load,
+ * except for KT_SEL_EXHAUSTIVE, which times every compiled configuration for
+ * an unseen shape once (on scratch buffers the handle allocates) and caches
+ * the winner. */
+kt_status kt_select(kt_handle h, const kt_shape* s, int32_t* config_id);
+
+/* Same for n shapes on the device: d_shapes and d_ids are device arrays. */
+kt_status kt_select_batch(kt_handle h, const kt_shape* d_shapes, int32_t n, int32_t* d_ids,
+                          void* stream);
+
+/* Inspect the fitted tree: node arrays in pre-order (left child first);
+ * feature = -1 marks a leaf, whose class indexes `chosen`.  Pass NULL arrays
+ * to query *n_nodes only. */
+kt_status kt_get_tree(kt_handle h, int32_t* n_nodes, int32_t* feature, int64_t* threshold,
+                      int32_t* left, int32_t* right, int32_t* cls);
+
+/* Save / load the selector state (kind, chosen ids, tree or MLP weights). */
+kt_status kt_save(kt_handle h, const char* path);
+kt_status kt_load(kt_handle h, const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KT_H */

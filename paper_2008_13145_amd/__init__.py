@@ -1,0 +1,344 @@
+"""kt: ML-pruned, per-shape-selected GEMM kernels for AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libkt.so`` (C ABI in ``include/kt.h``).  Every
+function only marshals arguments; all work runs in the native library.  The
+library must be built first (``python -m paper_2008_13145_amd.build``);
+loading fails loudly otherwise -- there is no fallback implementation.
+
+Device buffers are passed as integers (device addresses) or as objects with a
+``data_ptr()`` method (e.g. torch tensors); streams as integers (hipStream_t)
+or objects with a ``cuda_stream`` attribute.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("KT_LIBRARY", os.path.join(HERE, "libkt.so"))
+
+F32, BF16, FP8E4M3 = 0, 1, 2
+NORM_RELATIVE, NORM_RAWCUT, NORM_STDCUT, NORM_SIGMOID = 0, 1, 2, 3
+SEL_DT_A, SEL_DT_B, SEL_DT_C, SEL_MLP, SEL_EXHAUSTIVE = 0, 1, 2, 3, 4
+
+STATUS = {0: "KT_OK", -1: "KT_EINVAL", -2: "KT_EUNSUPPORTED", -3: "KT_EHIP",
+          -4: "KT_ENOTFITTED", -5: "KT_EWORKSPACE", -6: "KT_EIO"}
+
+c_i32, c_i64, c_u64, c_f32, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                          ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t)
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("M", c_i64), ("N", c_i64), ("K", c_i64), ("batch", c_i64),
+                ("transA", c_i32), ("transB", c_i32)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("bm", c_i32), ("bn", c_i32), ("t", c_i32), ("bk", c_i32), ("dtype", c_i32)]
+
+
+class SweepOpts(ctypes.Structure):
+    _fields_ = [("warmup", c_i32), ("target_ms", c_f32), ("min_reps", c_i32), ("max_reps", c_i32),
+                ("cut_factor", c_f32), ("pause_ms", c_f32), ("seed", c_u64),
+                ("alpha", c_f32), ("beta", c_f32)]
+
+
+class MlpOpts(ctypes.Structure):
+    _fields_ = [("steps", c_i32), ("lr", c_f32), ("init", ctypes.POINTER(c_f32)), ("seed", c_u64)]
+
+
+class KtError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_SIGS = {
+    "kt_create": (c_i32, [ctypes.POINTER(c_vp), ctypes.c_int]),
+    "kt_destroy": (c_i32, [c_vp]),
+    "kt_last_error": (ctypes.c_char_p, [c_vp]),
+    "kt_abi_version": (c_i32, []),
+    "kt_num_configs": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
+    "kt_get_config": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(Config)]),
+    "kt_config_compiled": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_i32)]),
+    "kt_gemm": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_f32, c_vp, c_i64, c_i64, c_vp, c_i64,
+                        c_i64, c_f32, c_vp, c_i64, c_i64, c_vp, c_vp, c_i32, c_vp]),
+    "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
+    "kt_sweep_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "kt_sweep": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_i32,
+                         ctypes.POINTER(SweepOpts), c_vp, c_sz, c_vp, c_vp]),
+    "kt_normalize": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
+    "kt_prune_workspace_bytes": (c_i32, [c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "kt_prune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
+                         c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
+    "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp]),
+    "kt_fit_selector": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp, c_i32,
+                                ctypes.POINTER(MlpOpts), c_vp, c_sz, c_vp]),
+    "kt_select": (c_i32, [c_vp, ctypes.POINTER(Shape), ctypes.POINTER(c_i32)]),
+    "kt_select_batch": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "kt_get_tree": (c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "kt_save": (c_i32, [c_vp, ctypes.c_char_p]),
+    "kt_load": (c_i32, [c_vp, ctypes.c_char_p]),
+}
+
+_lib = None
+
+
+def lib(path: str | None = None):
+    """Load libkt.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2008_13145_amd.build` "
+                           "(the GPU library has no fallback)")
+    L = ctypes.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = L
+    return L
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take a pointer of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def shape(M, N, K, batch=1, transA=0, transB=0) -> Shape:
+    return Shape(int(M), int(N), int(K), int(batch), int(transA), int(transB))
+
+
+def shapes_array(rows):
+    """Array of Shape from an iterable of (M, N, K, batch, transA, transB)."""
+    rows = list(rows)
+    arr = (Shape * max(1, len(rows)))()
+    for i, r in enumerate(rows):
+        arr[i] = shape(*r)
+    return arr
+
+
+class Handle:
+    """One kt handle (``device=-1`` for a host-only handle)."""
+
+    def __init__(self, device: int = 0, libpath: str | None = None):
+        self.L = lib(libpath)
+        h = c_vp()
+        st = self.L.kt_create(ctypes.byref(h), int(device))
+        if st != 0:
+            raise KtError(st, self.L.kt_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.L.kt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise KtError(st, self.L.kt_last_error(self.h).decode())
+
+    def status(self, st):
+        """Return (status, message) without raising."""
+        return st, (self.L.kt_last_error(self.h).decode() if st != 0 else "")
+
+    # ------------------------------------------------------------ configs
+    def num_configs(self, dtype=F32) -> int:
+        n = c_i32()
+        self._check(self.L.kt_num_configs(self.h, dtype, ctypes.byref(n)))
+        return n.value
+
+    def get_config(self, id, dtype=F32):
+        c = Config()
+        self._check(self.L.kt_get_config(self.h, dtype, int(id), ctypes.byref(c)))
+        return (c.bm, c.bn, c.t, c.bk)
+
+    def configs(self, dtype=F32):
+        return [self.get_config(i, dtype) for i in range(self.num_configs(dtype))]
+
+    def config_compiled(self, id, transA, transB, dtype=F32) -> bool:
+        v = c_i32()
+        self._check(self.L.kt_config_compiled(self.h, dtype, int(id), int(transA), int(transB),
+                                              ctypes.byref(v)))
+        return bool(v.value)
+
+    # --------------------------------------------------------------- gemm
+    def gemm_raw(self, dtype, shp: Shape, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
+                 scaleA=None, scaleB=None, config_id=-1, stream=None, check=True):
+        st = self.L.kt_gemm(self.h, dtype, ctypes.byref(shp), float(alpha), _ptr(A), int(lda),
+                            int(sA), _ptr(B), int(ldb), int(sB), float(beta), _ptr(C), int(ldc),
+                            int(sC), _ptr(scaleA), _ptr(scaleB), int(config_id), _stream(stream))
+        if check:
+            self._check(st)
+        return st
+
+    def gemm(self, A, B, C, transA=0, transB=0, alpha=1.0, beta=0.0, config_id=-1, dtype=F32,
+             scaleA=None, scaleB=None, stream=None):
+        """Batched GEMM on 3-D (or 2-D) row-major device tensors: A is
+        (batch, M, K) or (batch, K, M) when transA, B is (batch, K, N) or
+        (batch, N, K), C is (batch, M, N).  Leading dimensions and batch
+        strides are read from the tensors' strides."""
+        def dims(t):
+            # strides of size-1 dimensions carry no information and are ignored
+            if t.dim() == 2:
+                t = t.unsqueeze(0)
+            b, r, c = t.shape
+            if c > 1 and t.stride(2) != 1:
+                raise ValueError("innermost dimension must be contiguous")
+            ld = t.stride(1) if r > 1 else max(c, 1)
+            st = t.stride(0) if b > 1 else r * ld
+            return b, r, c, ld, st
+        ba, ra, ca, lda, sA = dims(A)
+        bb, rb, cb, ldb, sB = dims(B)
+        bc, M, N, ldc, sC = dims(C)
+        K = ra if transA else ca
+        if (ca if transA else ra) != M or (rb if transB else cb) != N or (cb if transB else rb) != K:
+            raise ValueError("inconsistent operand shapes")
+        return self.gemm_raw(dtype, shape(M, N, K, bc, transA, transB), alpha, A, lda, sA, B, ldb,
+                             sB, beta, C, ldc, sC, scaleA, scaleB, config_id, stream)
+
+    def fill_uniform(self, dst, n, seed, offset=0, stream=None):
+        self._check(self.L.kt_fill_uniform(self.h, _ptr(dst), int(n), int(seed) & (2 ** 64 - 1),
+                                           int(offset), _stream(stream)))
+
+    # -------------------------------------------------------------- sweep
+    @staticmethod
+    def sweep_workspace_bytes(shapes, dtype=F32) -> int:
+        arr = shapes_array(shapes)
+        b = c_sz()
+        st = lib().kt_sweep_workspace_bytes(arr, len(shapes), dtype, ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "sweep workspace query")
+        return b.value
+
+    def sweep(self, shapes, workspace, ws_bytes, config_ids=None, time_ns=None, warmup=1,
+              target_ms=2.0, min_reps=3, max_reps=200, cut_factor=8.0, pause_ms=0.0, seed=13145,
+              alpha=1.0, beta=0.0, dtype=F32, stream=None):
+        arr = shapes_array(shapes)
+        n_cfg = self.num_configs(dtype) if config_ids is None else len(config_ids)
+        if time_ns is None:
+            time_ns = np.full((len(shapes), n_cfg), -1, dtype=np.int64)
+        assert time_ns.dtype == np.int64 and time_ns.flags.c_contiguous
+        assert time_ns.shape == (len(shapes), n_cfg)
+        ids = None
+        if config_ids is not None:
+            ids = np.ascontiguousarray(config_ids, dtype=np.int32)
+        opts = SweepOpts(warmup, target_ms, min_reps, max_reps, cut_factor, pause_ms,
+                         int(seed) & (2 ** 64 - 1), alpha, beta)
+        self._check(self.L.kt_sweep(self.h, dtype, arr, len(shapes),
+                                    None if ids is None else ids.ctypes.data, n_cfg,
+                                    ctypes.byref(opts), _ptr(workspace), int(ws_bytes),
+                                    _stream(stream), time_ns.ctypes.data))
+        return time_ns
+
+    # -------------------------------------------------- normalize / prune
+    def normalize(self, d_time, n_rows, n_configs, norm, d_out, stream=None):
+        self._check(self.L.kt_normalize(self.h, _ptr(d_time), int(n_rows), int(n_configs), int(norm),
+                                        _ptr(d_out), _stream(stream)))
+
+    @staticmethod
+    def prune_workspace_bytes(n_rows, n_configs, k, n_init) -> int:
+        b = c_sz()
+        st = lib().kt_prune_workspace_bytes(n_rows, n_configs, k, n_init, ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "prune workspace query")
+        return b.value
+
+    def prune(self, time_ns, k, norm=NORM_RELATIVE, seed=13145, n_init=10, max_iter=300,
+              workspace=None, ws_bytes=0, stream=None):
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        n, d = T.shape
+        chosen = np.zeros(k, dtype=np.int32)
+        labels = np.zeros(n, dtype=np.int32)
+        cents = np.zeros((k, d), dtype=np.int64)
+        inertia = c_i64()
+        self._check(self.L.kt_prune(self.h, T.ctypes.data, n, d, int(k), int(norm),
+                                    int(seed) & (2 ** 64 - 1), int(n_init), int(max_iter),
+                                    _ptr(workspace), int(ws_bytes), _stream(stream),
+                                    chosen.ctypes.data, ctypes.byref(inertia), labels.ctypes.data,
+                                    cents.ctypes.data))
+        return dict(chosen=chosen.tolist(), inertia=inertia.value, labels=labels, centroids=cents)
+
+    def prune_topn(self, time_ns, k):
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        chosen = np.zeros(k, dtype=np.int32)
+        self._check(self.L.kt_prune_topn(self.h, T.ctypes.data, T.shape[0], T.shape[1], int(k),
+                                         chosen.ctypes.data))
+        return chosen.tolist()
+
+    # ------------------------------------------------------------- select
+    def fit_selector(self, kind, shapes, time_ns, chosen, mlp_steps=3000, mlp_lr=1e-3,
+                     mlp_init=None, mlp_seed=13150, workspace=None, ws_bytes=0, stream=None):
+        arr = shapes_array(shapes)
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        ch = np.ascontiguousarray(chosen, dtype=np.int32)
+        opts = None
+        keep = None
+        if kind == SEL_MLP:
+            init_ptr = None
+            if mlp_init is not None:
+                keep = np.ascontiguousarray(mlp_init, dtype=np.float32)
+                init_ptr = keep.ctypes.data_as(ctypes.POINTER(c_f32))
+            opts = MlpOpts(int(mlp_steps), float(mlp_lr), init_ptr, int(mlp_seed))
+        self._check(self.L.kt_fit_selector(self.h, int(kind), arr, T.ctypes.data, T.shape[0],
+                                           T.shape[1], ch.ctypes.data, len(ch),
+                                           None if opts is None else ctypes.byref(opts),
+                                           _ptr(workspace), int(ws_bytes), _stream(stream)))
+        del keep
+
+    def select(self, M, N, K, batch=1, transA=0, transB=0) -> int:
+        v = c_i32()
+        s = shape(M, N, K, batch, transA, transB)
+        self._check(self.L.kt_select(self.h, ctypes.byref(s), ctypes.byref(v)))
+        return v.value
+
+    def select_batch(self, d_shapes, n, d_ids, stream=None):
+        self._check(self.L.kt_select_batch(self.h, _ptr(d_shapes), int(n), _ptr(d_ids),
+                                           _stream(stream)))
+
+    def get_tree(self):
+        n = c_i32()
+        self._check(self.L.kt_get_tree(self.h, ctypes.byref(n), None, None, None, None, None))
+        f = np.zeros(n.value, np.int32)
+        t = np.zeros(n.value, np.int64)
+        l = np.zeros(n.value, np.int32)
+        r = np.zeros(n.value, np.int32)
+        c = np.zeros(n.value, np.int32)
+        self._check(self.L.kt_get_tree(self.h, ctypes.byref(n), f.ctypes.data, t.ctypes.data,
+                                       l.ctypes.data, r.ctypes.data, c.ctypes.data))
+        return dict(feature=f.tolist(), threshold=t.tolist(), left=l.tolist(), right=r.tolist(),
+                    cls=c.tolist())
+
+    def save(self, path):
+        self._check(self.L.kt_save(self.h, path.encode()))
+
+    def load(self, path):
+        self._check(self.L.kt_load(self.h, path.encode()))

@@ -1,0 +1,321 @@
+// FP32 tiled GEMM family for gfx950: C_b = alpha * op(A_b) * op(B_b) + beta * C_b.
+//
+// One kernel template covers the whole configuration space.  The paper's
+// kernel (section 3) gives each work item an R x A tile of the left input and
+// an A x C tile of the right one, with no local memory; on CDNA4 the same
+// three knobs become: a BM x BN work-group tile staged through LDS in BK-deep
+// slices (double buffered), and a per-wave (8T) x (8T) output block computed
+// by MFMA, i.e. T*T accumulators per lane:
+//
+//   T = 1: 8x8 wave block, v_mfma_f32_4x4x1f32 (16 blocks): 4 output blocks
+//          x 4-way K split, reduced with cross-lane shuffles at the end;
+//   T = 2: 16x16 wave block, v_mfma_f32_16x16x4f32;
+//   T = 4: 32x32 wave block, v_mfma_f32_32x32x2f32;
+//   T = 8: 64x64 wave block, 2x2 v_mfma_f32_32x32x2f32.
+//
+// LDS holds both operands K-major (As[k][m], Bs[k][n]) so every MFMA operand
+// read is a run of consecutive addresses.  An operand whose global storage
+// is contiguous along K is transposed on the way in (row pad 2 keeps those
+// scattered writes on distinct banks); an operand contiguous along M/N is
+// copied straight (no pad, 16-byte vector writes).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kt {
+
+struct GemmArgs {
+  int64_t M, N, K, batch;
+  const void* A; int64_t lda, sA;
+  const void* B; int64_t ldb, sB;
+  float* C; int64_t ldc, sC;
+  float alpha, beta;
+  const float* scaleA; const float* scaleB;   // FP8 only
+  int32_t vecA, vecB;   // 16-byte vector loads allowed (pointer, ld, stride aligned)
+  int32_t tiles_m, tiles_n;
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Work-group id -> (tile_m, tile_n).  Consecutive work-group ids land on
+// different XCDs (round robin over 8), so the id is first remapped to give
+// each XCD a contiguous range of tiles; tiles are then walked in groups of
+// 8 tile-rows so that neighbours share A row panels and B column panels in
+// that XCD's L2.
+__device__ __forceinline__ void tile_coords(int64_t pid, int tiles_m, int tiles_n, int& tm,
+                                            int& tn) {
+  const int64_t nt = (int64_t)tiles_m * tiles_n;
+  const int64_t per = nt / 8;
+  int64_t t = pid;
+  if (pid < per * 8) t = (pid % 8) * per + pid / 8;
+  const int64_t group = 8;
+  const int64_t width = group * tiles_n;
+  const int64_t gid = t / width;
+  const int64_t first_m = gid * group;
+  const int64_t gsz = (tiles_m - first_m) < group ? (tiles_m - first_m) : group;
+  const int64_t r = t % width;
+  tm = (int)(first_m + r % gsz);
+  tn = (int)(r / gsz);
+}
+
+// Global -> register staging of one ROWS x COLS tile whose COLS dimension is
+// contiguous in memory (row stride ld).  Rows beyond row_lim or columns beyond
+// col_lim read as zero.
+template <int ROWS, int COLS, int NT>
+struct TileLoader {
+  static constexpr int CV = COLS / 4;                 // float4 chunks per row
+  static constexpr int NV = ROWS * CV;                // chunks in the tile
+  static constexpr int VPT = (NV + NT - 1) / NT;      // chunks per thread
+  f32x4 v[VPT];
+
+  __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int64_t row0,
+                                       int64_t col0, int64_t row_lim, int64_t col_lim, bool vec,
+                                       int tid) {
+    const bool full = vec && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int c = tid + i * NT;
+      if (NV % NT != 0 && c >= NV) { v[i] = f32x4{0.f, 0.f, 0.f, 0.f}; continue; }
+      const int r = c / CV, q = (c % CV) * 4;
+      const int64_t gr = row0 + r, gc = col0 + q;
+      const float* p = base + gr * ld + gc;
+      if (full) {
+        v[i] = *reinterpret_cast<const f32x4*>(p);
+      } else {
+        f32x4 t = {0.f, 0.f, 0.f, 0.f};
+        if (gr < row_lim) {
+          if (vec && gc + 4 <= col_lim) {
+            t = *reinterpret_cast<const f32x4*>(p);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (gc + e < col_lim) t[e] = p[e];
+          }
+        }
+        v[i] = t;
+      }
+    }
+  }
+
+  // Store into an LDS array laid out [COLS][LD] (transpose: element (r, c) goes
+  // to lds[c * LD + r]) or [ROWS][LD] (direct: lds[r * LD + c]).
+  template <bool TRANSPOSE, int LD>
+  __device__ __forceinline__ void store(float* lds, int tid) const {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int c = tid + i * NT;
+      if (NV % NT != 0 && c >= NV) continue;
+      const int r = c / CV, q = (c % CV) * 4;
+      if (TRANSPOSE) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) lds[(q + e) * LD + r] = v[i][e];
+      } else {
+        *reinterpret_cast<f32x4*>(lds + r * LD + q) = v[i];
+      }
+    }
+  }
+};
+
+template <int BM, int BN, int T, int BK, int TA, int TB>
+struct GemmF32Cfg {
+  static constexpr int WT = 8 * T;                     // wave block edge
+  static constexpr int WAVES_M = BM / WT;
+  static constexpr int WAVES_N = BN / WT;
+  static constexpr int WAVES = WAVES_M * WAVES_N;
+  static constexpr int NT = WAVES * 64;
+  // A operand tile: op(A) rows m, depth k.  TA == 0 -> stored with k contiguous
+  // (transpose into LDS), TA == 1 -> m contiguous (direct copy).
+  static constexpr int LDA_S = BM + (TA == 0 ? 2 : 0);
+  static constexpr int LDB_S = BN + (TB == 1 ? 2 : 0);
+  static constexpr int A_STAGE = BK * LDA_S;
+  static constexpr int B_STAGE = BK * LDB_S;
+  static constexpr int LDS_FLOATS = 2 * (A_STAGE + B_STAGE);
+  static_assert(BM % WT == 0 && BN % WT == 0, "tile must hold whole wave blocks");
+  static_assert(WAVES >= 1 && WAVES <= 16, "1..16 waves per work-group");
+  static_assert(LDS_FLOATS * 4 <= 160 * 1024, "LDS budget");
+  static_assert(BK % 4 == 0, "BK multiple of 4");
+};
+
+template <int BM, int BN, int T, int BK, int TA, int TB>
+__global__ void __launch_bounds__(BM * BN / (T * T))
+gemm_f32_kernel(GemmArgs args) {
+  using Cfg = GemmF32Cfg<BM, BN, T, BK, TA, TB>;
+  constexpr int NT = Cfg::NT;
+  constexpr int WT = Cfg::WT;
+  __shared__ float lds[Cfg::LDS_FLOATS];
+  float* As = lds;                          // [2][BK][LDA_S]
+  float* Bs = lds + 2 * Cfg::A_STAGE;       // [2][BK][LDB_S]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / Cfg::WAVES_N) * WT;
+  const int wn0 = (wave % Cfg::WAVES_N) * WT;
+
+  int tm, tn;
+  tile_coords(blockIdx.x, args.tiles_m, args.tiles_n, tm, tn);
+  const int64_t bz = blockIdx.y;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = args.M, N = args.N, K = args.K;
+  const float* __restrict__ Ag = static_cast<const float*>(args.A) + bz * args.sA;
+  const float* __restrict__ Bg = static_cast<const float*>(args.B) + bz * args.sB;
+  const bool vecA = args.vecA != 0, vecB = args.vecB != 0;
+
+  // Loaders: the tile's contiguous dimension is the loader's COLS.
+  TileLoader<(TA ? BK : BM), (TA ? BM : BK), NT> la;
+  TileLoader<(TB ? BN : BK), (TB ? BK : BN), NT> lb;
+
+  auto load_stage = [&](int64_t k0) {
+    if (TA) la.load(Ag, args.lda, k0, m0, K, M, vecA, tid);
+    else    la.load(Ag, args.lda, m0, k0, M, K, vecA, tid);
+    if (TB) lb.load(Bg, args.ldb, n0, k0, N, K, vecB, tid);
+    else    lb.load(Bg, args.ldb, k0, n0, K, N, vecB, tid);
+  };
+  auto store_stage = [&](int buf) {
+    la.template store<TA == 0, Cfg::LDA_S>(As + buf * Cfg::A_STAGE, tid);
+    lb.template store<TB == 1, Cfg::LDB_S>(Bs + buf * Cfg::B_STAGE, tid);
+  };
+
+  // Accumulators: T*T floats per lane.
+  constexpr int NACC = (T == 1) ? 4 : (T == 2) ? 4 : (T == 4) ? 16 : 64;
+  float acc[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) acc[i] = 0.f;
+
+  const int nk = (int)((K + BK - 1) / BK);
+  if (nk > 0) {
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
+    const float* as = As + buf * Cfg::A_STAGE;
+    const float* bs = Bs + buf * Cfg::B_STAGE;
+    if constexpr (T == 1) {
+      // 16 blocks of 4x4x1: block b = lane/4 -> output block ob = b%4 of the
+      // 2x2 grid of 4x4 blocks, K offset ks = b/4.
+      const int b = lane >> 2, i = lane & 3;
+      const int ob = b & 3, ks = b >> 2;
+      const int ar = wm0 + 4 * (ob >> 1) + i;
+      const int bc = wn0 + 4 * (ob & 1) + i;
+      f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const float a = as[(kk + ks) * Cfg::LDA_S + ar];
+        const float bv = bs[(kk + ks) * Cfg::LDB_S + bc];
+        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bv, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = c[r];
+    } else if constexpr (T == 2) {
+      const int r16 = lane & 15, kq = lane >> 4;
+      f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const float a = as[(kk + kq) * Cfg::LDA_S + wm0 + r16];
+        const float bv = bs[(kk + kq) * Cfg::LDB_S + wn0 + r16];
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = c[r];
+    } else if constexpr (T == 4) {
+      const int r32 = lane & 31, kh = lane >> 5;
+      f32x16 c;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) c[r] = acc[r];
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        const float a = as[(kk + kh) * Cfg::LDA_S + wm0 + r32];
+        const float bv = bs[(kk + kh) * Cfg::LDB_S + wn0 + r32];
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = c[r];
+    } else {
+      const int r32 = lane & 31, kh = lane >> 5;
+      f32x16 c00, c01, c10, c11;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        c00[r] = acc[r]; c01[r] = acc[16 + r]; c10[r] = acc[32 + r]; c11[r] = acc[48 + r];
+      }
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        const float* ar = as + (kk + kh) * Cfg::LDA_S + wm0 + r32;
+        const float* br = bs + (kk + kh) * Cfg::LDB_S + wn0 + r32;
+        const float a0 = ar[0], a1 = ar[32];
+        const float b0 = br[0], b1 = br[32];
+        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, c01, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, c10, 0, 0, 0);
+        c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, c11, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        acc[r] = c00[r]; acc[16 + r] = c01[r]; acc[32 + r] = c10[r]; acc[48 + r] = c11[r];
+      }
+    }
+    if (kt + 1 < nk) store_stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue.
+  float* __restrict__ Cg = args.C + bz * args.sC;
+  const float alpha = args.alpha, beta = args.beta;
+  const int64_t ldc = args.ldc;
+  auto put = [&](int row, int col, float v) {
+    const int64_t gi = m0 + wm0 + row, gj = n0 + wn0 + col;
+    if (gi < M && gj < N) {
+      float* p = Cg + gi * ldc + gj;
+      float out = alpha * v;
+      if (beta != 0.f) out = fmaf(beta, *p, out);
+      *p = out;
+    }
+  };
+  if constexpr (T == 1) {
+    // Sum the four K slices (lanes differing in bits 4 and 5), then lane with
+    // slice s stores row s of its 4x4 block: 64 lanes store the 8x8 block.
+    float s[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float v = acc[r];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      s[r] = v;
+    }
+    const int ob = (lane >> 2) & 3, i = lane & 3, ks = lane >> 4;
+    float v = (ks == 0) ? s[0] : (ks == 1) ? s[1] : (ks == 2) ? s[2] : s[3];
+    put(4 * (ob >> 1) + ks, 4 * (ob & 1) + i, v);
+  } else if constexpr (T == 2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put((lane >> 4) * 4 + r, lane & 15, acc[r]);
+  } else if constexpr (T == 4) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) put((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3), lane & 31, acc[r]);
+  } else {
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) {
+      const int si = sub >> 1, sj = sub & 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        put(32 * si + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3), 32 * sj + (lane & 31),
+            acc[16 * (2 * si + sj) + r]);
+    }
+  }
+}
+
+// Host-side launcher of one instantiation on a stream.
+template <int BM, int BN, int T, int BK, int TA, int TB>
+hipError_t launch_gemm_f32(const GemmArgs& a, hipStream_t stream) {
+  using Cfg = GemmF32Cfg<BM, BN, T, BK, TA, TB>;
+  GemmArgs g = a;
+  g.tiles_m = (int)((a.M + BM - 1) / BM);
+  g.tiles_n = (int)((a.N + BN - 1) / BN);
+  dim3 grid((unsigned)((int64_t)g.tiles_m * g.tiles_n), (unsigned)a.batch, 1);
+  hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, T, BK, TA, TB>), grid, dim3(Cfg::NT), 0, stream, g);
+  return hipGetLastError();
+}
+
+}  // namespace kt

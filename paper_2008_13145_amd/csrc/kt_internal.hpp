@@ -1,0 +1,85 @@
+// Internal state of a kt handle and helpers shared by the host sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/kt.h"
+#include "gemm_f32.hpp"
+#include "registry.hpp"
+
+namespace kt {
+
+enum { NUM_DTYPES = 3 };
+
+struct Tree {
+  std::vector<int32_t> feature, left, right, cls;
+  std::vector<int64_t> threshold;
+};
+
+struct MlpModel {
+  int32_t k = 0;
+  std::vector<float> params;   // W1 b1 W2 b2 W3 b3 packed
+};
+
+struct ShapeKey {
+  int64_t M, N, K, batch;
+  int32_t ta, tb, dtype;
+  bool operator<(const ShapeKey& o) const {
+    return std::tie(M, N, K, batch, ta, tb, dtype) < std::tie(o.M, o.N, o.K, o.batch, o.ta, o.tb, o.dtype);
+  }
+};
+
+struct Ctx {
+  int device = -1;
+  std::string err;
+  // launcher lookup: [dtype][id * 4 + layout]
+  std::vector<LaunchFn> table[NUM_DTYPES];
+  std::vector<ConfigDef> configs[NUM_DTYPES];
+  // selector state
+  int32_t sel_kind = -1;           // kt_selector, -1 = none
+  std::vector<int32_t> chosen;     // deployed configuration ids
+  int32_t sel_dtype = KT_F32;
+  Tree tree;
+  MlpModel mlp;
+  void* d_tree = nullptr;          // device copy of the tree for batch selection
+  size_t d_tree_bytes = 0;
+  void* d_mlp = nullptr;
+  std::map<ShapeKey, int32_t> exhaustive_cache;
+  void* scratch = nullptr;         // exhaustive-selection operands (handle-owned)
+  size_t scratch_bytes = 0;
+  std::vector<uint16_t> sigmoid_lut;
+};
+
+// Record an error message on the handle and return the status.
+kt_status fail(Ctx* h, kt_status st, const std::string& msg);
+kt_status hip_fail(Ctx* h, hipError_t e, const char* what);
+bool need_device(Ctx* h);
+LaunchFn find_launcher(Ctx* h, int dtype, int32_t id, int ta, int tb);
+int layout_index(int ta, int tb);
+
+// Shape validation shared by gemm and sweep; returns KT_OK or KT_EINVAL with a message.
+kt_status check_gemm_args(Ctx* h, const kt_shape* s, int64_t lda, int64_t sA, int64_t ldb,
+                          int64_t sB, int64_t ldc, int64_t sC);
+// Launch one GEMM with a given configuration (no validation beyond lookup).
+kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const void* A,
+                      int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB,
+                      float beta, float* C, int64_t ldc, int64_t sC, const float* scaleA,
+                      const float* scaleB, int32_t cfg, hipStream_t stream);
+
+// Fill kernel launcher (device).
+hipError_t fill_uniform(float* dst, int64_t n, uint64_t seed, int64_t offset, hipStream_t s);
+
+// Selector helpers (select.cpp).
+kt_status select_config(Ctx* h, const kt_shape* s, int32_t* id);
+
+// Sigmoid lookup table of the normalization (Q16 -> Q16).
+const std::vector<uint16_t>& sigmoid_table(Ctx* h);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace kt

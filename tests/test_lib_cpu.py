@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI (no GPU needed): exports, configuration
+space, argument validation on a host-only handle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(kt_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_every_declared_symbol_is_exported(kt):
+    L = ctypes.CDLL(kt.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header(kt):
+    assert _declared() <= set(kt._SIGS) | {"kt_abi_version"}
+
+
+def test_config_space(kt):
+    from paper_2008_13145_amd import codegen
+    h = kt.Handle(-1)
+    cfgs = h.configs()
+    assert len(cfgs) == 164
+    assert cfgs == codegen.f32_configs()
+    by_t = {t: sum(1 for c in cfgs if c[2] == t) for t in (1, 2, 4, 8)}
+    assert by_t == {1: 60, 2: 52, 4: 36, 8: 16}
+    for (bm, bn, t, bk) in cfgs:
+        assert bm % (8 * t) == 0 and bn % (8 * t) == 0 and 1 <= bm * bn // (64 * t * t) <= 16
+        assert bk in (8, 16, 32, 64)
+    # every configuration is compiled for every layout in the full build
+    assert all(h.config_compiled(i, ta, tb) for i in range(164) for ta, tb in synth.LAYOUTS)
+    # the configuration of the single-GEMM workload (64x64 tile, 4x4 thread tile, BK 16)
+    assert (64, 64, 4, 16) in cfgs
+
+
+def test_host_handle_rejects_gpu_work(kt):
+    h = kt.Handle(-1)
+    s = kt.shape(8, 8, 8)
+    st = h.L.kt_gemm(h.h, 0, ctypes.byref(s), 1.0, None, 8, 0, None, 8, 0, 0.0, None, 8, 0,
+                     None, None, 0, None)
+    assert st == -1 and "device" in h.L.kt_last_error(h.h).decode()
+    with pytest.raises(kt.KtError):
+        h.get_config(164)
+    with pytest.raises(kt.KtError):
+        h.get_config(-1)
+
+
+def test_create_rejects_bad_device(kt):
+    with pytest.raises(kt.KtError):
+        kt.Handle(-7)
+
+
+def test_abi_version(kt):
+    assert kt.lib().kt_abi_version() == 100
+
+
+def test_sweep_workspace_query(kt):
+    n = kt.Handle.sweep_workspace_bytes([(100, 200, 300, 2, 0, 1)])
+    # A 2*100*300 + B 2*300*200 + C 2*100*200 floats, each region 256-aligned, plus scale slot
+    assert n >= 4 * (60000 + 120000 + 40000)
+    assert n % 256 == 0
