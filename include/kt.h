@@ -167,7 +167,8 @@ kt_status kt_sweep(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t 
 /* Normalize a device int64 time table [n_rows][n_configs] into device uint16
  * Q16 values (section 3.4): q = round_half_up(65535 * t_best / t) with t_best
  * the row's smallest positive time (t <= 0 gives 0), then the chosen variant.
- * Runs on `stream`, asynchronously. */
+ * Runs on `stream`, asynchronously.  The first call on a handle uploads the
+ * 128 KiB sigmoid table into device memory the handle owns. */
 kt_status kt_normalize(kt_handle h, const int64_t* d_time, int32_t n_rows, int32_t n_configs,
                        kt_norm norm, uint16_t* d_out, void* stream);
 
@@ -181,7 +182,8 @@ kt_status kt_prune_workspace_bytes(int32_t n_rows, int32_t n_configs, int32_t k,
  * k-means++ initialisation from a SplitMix64 stream seeded with seed + r for
  * restart r, integer Lloyd iterations (exact int64 distances and sums,
  * rounded-mean centroids), n_init restarts (lowest inertia wins, lowest r on
- * ties), at most max_iter updates each.  Centroid j yields its best
+ * ties), at most max_iter updates each.  Limits: n_rows <= 4096,
+ * k <= 64, k * n_configs <= 8192.  Centroid j yields its best
  * configuration not already chosen.  Outputs (host): chosen[k] column
  * indices in cluster order, *inertia_out, and optionally labels[n_rows] and
  * centroids[k * n_configs] (NULL to skip).  Synchronizes `stream`. */
@@ -191,10 +193,13 @@ kt_status kt_prune(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t 
                    int32_t* chosen, int64_t* inertia_out, int32_t* labels, int64_t* centroids);
 
 /* Top-N baseline of section 4.2: the k configurations that are best (largest
- * normalized value, lowest index on ties) for the most rows, ties in the
- * count to the lower index.  Host tables in and out. */
+ * relative value, lowest index on ties) for the most rows, ties in the count
+ * to the lower index.  time_ns and chosen are host arrays; the workspace is
+ * sized by kt_prune_workspace_bytes(n_rows, n_configs, 1, 1).  Synchronizes
+ * `stream`. */
 kt_status kt_prune_topn(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
-                        int32_t k, int32_t* chosen);
+                        int32_t k, void* workspace, size_t ws_bytes, void* stream,
+                        int32_t* chosen);
 
 /* ------------------------------------------------------------- selection */
 
@@ -203,8 +208,10 @@ typedef struct {
   float lr;               /* default 1e-3 */
   const float* init;      /* host, optional: W1 (64x6), b1, W2 (64x64), b2, W3 (k x 64), b3
                              packed in that order, row-major [out][in]; NULL = He-uniform
-                             from SplitMix64(seed) */
+                             U(+-sqrt(6/fan_in)) from SplitMix64(seed), zero biases */
   uint64_t seed;
+  int32_t graph_steps;    /* > 1: capture this many steps in a hipGraph and replay it;
+                             0 or 1: launch every step directly */
 } kt_mlp_opts;
 
 /* Fit the runtime selector on n_rows problems (section 5.1).  shapes and
@@ -236,9 +243,38 @@ kt_status kt_select_batch(kt_handle h, const kt_shape* d_shapes, int32_t n, int3
 kt_status kt_get_tree(kt_handle h, int32_t* n_nodes, int32_t* feature, int64_t* threshold,
                       int32_t* left, int32_t* right, int32_t* cls);
 
-/* Save / load the selector state (kind, chosen ids, tree or MLP weights). */
+/* Save / load the selector state (kind, chosen ids, tree or MLP weights) as
+ * a versioned text file.  kt_load returns KT_EIO for a missing or malformed
+ * file and leaves the handle unchanged in that case. */
 kt_status kt_save(kt_handle h, const char* path);
 kt_status kt_load(kt_handle h, const char* path);
+
+/* ------------------------------------------------------- MLP cost model */
+
+/* The learned selector: 6 -> 64 -> 64 -> k network (ReLU, linear output) on
+ * features [log2 M/12, log2 N/12, log2 K/12, log2 batch/6, transA, transB]
+ * regressing the relative performance of the k chosen kernels (MSE); the
+ * selection is the argmax.  Parameters are packed W1 b1 W2 b2 W3 b3 (FP32). */
+
+/* Workspace bytes for kt_fit_selector(KT_SEL_MLP). */
+kt_status kt_mlp_workspace_bytes(int32_t n_rows, int32_t n_configs, int32_t k, size_t* bytes);
+/* Number of packed parameters for k outputs (5128 for k = 8). */
+kt_status kt_mlp_num_params(int32_t k, int32_t* n_params);
+/* Features of n device shapes into d_X[n][6] (device, FP32). */
+kt_status kt_mlp_features(kt_handle h, const kt_shape* d_shapes, int32_t n, float* d_X, void* stream);
+/* One full-batch forward (and backward) pass with the training kernels, at
+ * the given device parameters: predictions d_pred[n][k] (optional), the
+ * gradient of the mean squared error w.r.t. every parameter d_grad (optional,
+ * packed like the parameters) and the sum of squared errors d_loss[0]
+ * (optional; the loss is that over n*k).  Gradients need d_Y[n][k] and a
+ * workspace of nblocks*(n_params*4) + nblocks*4 bytes (256-aligned parts),
+ * nblocks = ceil(n / 64); kt_mlp_workspace_bytes is always enough. */
+kt_status kt_mlp_forward_backward(kt_handle h, const float* d_params, const float* d_X,
+                                  const float* d_Y, int32_t n, int32_t k, float* d_pred,
+                                  float* d_grad, float* d_loss, void* workspace, size_t ws_bytes,
+                                  void* stream);
+/* Copy the fitted MLP parameters (host).  NULL params queries *n_params. */
+kt_status kt_get_mlp(kt_handle h, int32_t* n_params, float* params);
 
 #ifdef __cplusplus
 }

@@ -46,7 +46,8 @@ class SweepOpts(ctypes.Structure):
 
 
 class MlpOpts(ctypes.Structure):
-    _fields_ = [("steps", c_i32), ("lr", c_f32), ("init", ctypes.POINTER(c_f32)), ("seed", c_u64)]
+    _fields_ = [("steps", c_i32), ("lr", c_f32), ("init", ctypes.POINTER(c_f32)), ("seed", c_u64),
+                ("graph_steps", c_i32)]
 
 
 class KtError(RuntimeError):
@@ -74,7 +75,7 @@ _SIGS = {
     "kt_prune_workspace_bytes": (c_i32, [c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_prune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                          c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
-    "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp]),
+    "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp, c_vp]),
     "kt_fit_selector": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp, c_i32,
                                 ctypes.POINTER(MlpOpts), c_vp, c_sz, c_vp]),
     "kt_select": (c_i32, [c_vp, ctypes.POINTER(Shape), ctypes.POINTER(c_i32)]),
@@ -82,6 +83,12 @@ _SIGS = {
     "kt_get_tree": (c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp]),
     "kt_save": (c_i32, [c_vp, ctypes.c_char_p]),
     "kt_load": (c_i32, [c_vp, ctypes.c_char_p]),
+    "kt_mlp_workspace_bytes": (c_i32, [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "kt_mlp_num_params": (c_i32, [c_i32, ctypes.POINTER(c_i32)]),
+    "kt_mlp_features": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "kt_mlp_forward_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp,
+                                        c_vp, c_sz, c_vp]),
+    "kt_get_mlp": (c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp]),
 }
 
 _lib = None
@@ -287,16 +294,18 @@ class Handle:
                                     cents.ctypes.data))
         return dict(chosen=chosen.tolist(), inertia=inertia.value, labels=labels, centroids=cents)
 
-    def prune_topn(self, time_ns, k):
+    def prune_topn(self, time_ns, k, workspace=None, ws_bytes=0, stream=None):
         T = np.ascontiguousarray(time_ns, dtype=np.int64)
         chosen = np.zeros(k, dtype=np.int32)
         self._check(self.L.kt_prune_topn(self.h, T.ctypes.data, T.shape[0], T.shape[1], int(k),
+                                         _ptr(workspace), int(ws_bytes), _stream(stream),
                                          chosen.ctypes.data))
         return chosen.tolist()
 
     # ------------------------------------------------------------- select
     def fit_selector(self, kind, shapes, time_ns, chosen, mlp_steps=3000, mlp_lr=1e-3,
-                     mlp_init=None, mlp_seed=13150, workspace=None, ws_bytes=0, stream=None):
+                     mlp_init=None, mlp_seed=13150, mlp_graph_steps=25, workspace=None, ws_bytes=0,
+                     stream=None):
         arr = shapes_array(shapes)
         T = np.ascontiguousarray(time_ns, dtype=np.int64)
         ch = np.ascontiguousarray(chosen, dtype=np.int32)
@@ -307,7 +316,7 @@ class Handle:
             if mlp_init is not None:
                 keep = np.ascontiguousarray(mlp_init, dtype=np.float32)
                 init_ptr = keep.ctypes.data_as(ctypes.POINTER(c_f32))
-            opts = MlpOpts(int(mlp_steps), float(mlp_lr), init_ptr, int(mlp_seed))
+            opts = MlpOpts(int(mlp_steps), float(mlp_lr), init_ptr, int(mlp_seed), int(mlp_graph_steps))
         self._check(self.L.kt_fit_selector(self.h, int(kind), arr, T.ctypes.data, T.shape[0],
                                            T.shape[1], ch.ctypes.data, len(ch),
                                            None if opts is None else ctypes.byref(opts),
@@ -342,3 +351,37 @@ class Handle:
 
     def load(self, path):
         self._check(self.L.kt_load(self.h, path.encode()))
+
+    # ---------------------------------------------------------------- mlp
+    @staticmethod
+    def mlp_workspace_bytes(n_rows, n_configs, k) -> int:
+        b = c_sz()
+        st = lib().kt_mlp_workspace_bytes(n_rows, n_configs, k, ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "MLP workspace query")
+        return b.value
+
+    @staticmethod
+    def mlp_num_params(k) -> int:
+        v = c_i32()
+        st = lib().kt_mlp_num_params(k, ctypes.byref(v))
+        if st != 0:
+            raise KtError(st, "MLP parameter count")
+        return v.value
+
+    def mlp_features(self, d_shapes, n, d_X, stream=None):
+        self._check(self.L.kt_mlp_features(self.h, _ptr(d_shapes), int(n), _ptr(d_X), _stream(stream)))
+
+    def mlp_forward_backward(self, d_params, d_X, d_Y, n, k, d_pred=None, d_grad=None, d_loss=None,
+                             workspace=None, ws_bytes=0, stream=None):
+        self._check(self.L.kt_mlp_forward_backward(self.h, _ptr(d_params), _ptr(d_X), _ptr(d_Y),
+                                                   int(n), int(k), _ptr(d_pred), _ptr(d_grad),
+                                                   _ptr(d_loss), _ptr(workspace), int(ws_bytes),
+                                                   _stream(stream)))
+
+    def get_mlp(self):
+        n = c_i32()
+        self._check(self.L.kt_get_mlp(self.h, ctypes.byref(n), None))
+        out = np.zeros(n.value, dtype=np.float32)
+        self._check(self.L.kt_get_mlp(self.h, ctypes.byref(n), out.ctypes.data))
+        return out

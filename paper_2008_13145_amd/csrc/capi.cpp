@@ -172,6 +172,7 @@ kt_status kt_destroy(kt_handle hh) {
     if (h->d_tree) (void)hipFree(h->d_tree);
     if (h->d_mlp) (void)hipFree(h->d_mlp);
     if (h->scratch) (void)hipFree(h->scratch);
+    if (h->d_lut) (void)hipFree(h->d_lut);
   }
   delete h;
   return KT_OK;

@@ -53,6 +53,7 @@ struct Ctx {
   void* scratch = nullptr;         // exhaustive-selection operands (handle-owned)
   size_t scratch_bytes = 0;
   std::vector<uint16_t> sigmoid_lut;
+  void* d_lut = nullptr;           // device sigmoid table (handle-owned)
 };
 
 // Record an error message on the handle and return the status.
@@ -74,8 +75,14 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
 // Fill kernel launcher (device).
 hipError_t fill_uniform(float* dst, int64_t n, uint64_t seed, int64_t offset, hipStream_t s);
 
-// Selector helpers (select.cpp).
+// Selector helpers (select.hip, mlp.hip).
 kt_status select_config(Ctx* h, const kt_shape* s, int32_t* id);
+kt_status mlp_select_host(Ctx* h, const kt_shape* s, int32_t* id);
+kt_status mlp_select_batch(Ctx* h, const kt_shape* d_shapes, int32_t n, int32_t* d_ids, hipStream_t st);
+kt_status mlp_upload(Ctx* h);
+kt_status fit_mlp(Ctx* h, const kt_shape* shapes, const int64_t* time_ns, int32_t n, int32_t d,
+                  const int32_t* chosen, int32_t k, const kt_mlp_opts* o, void* ws, size_t ws_bytes,
+                  hipStream_t st);
 
 // Sigmoid lookup table of the normalization (Q16 -> Q16).
 const std::vector<uint16_t>& sigmoid_table(Ctx* h);

@@ -1,0 +1,468 @@
+// Runtime kernel selection (section 5 of the paper, "Deploying the kernels").
+//
+// Each training problem is labelled with the chosen kernel that ran it
+// fastest, and a decision tree on the matrix sizes learns that label
+// (section 5.1, trees A/B/C).  At launch time the tree is walked -- the
+// paper's nested if statements in the kernel launcher -- to pick one of the
+// deployed configurations.  Exhaustive search (time every compiled
+// configuration once per unseen shape, then cache) is the fallback selector
+// and the judge of a selector's regret.
+//
+// Integer CART: features (M, N, K, batch, transA, transB) as raw integers;
+// Gini criterion with splits scored by S = A/n_L + B/n_R (A, B the sums of
+// squared class counts of each side), compared exactly by cross-
+// multiplication; thresholds floor(sqrt(a*b)) between consecutive distinct
+// values; x <= t goes left; first maximum over features 0..5 and ascending
+// thresholds; a split must strictly beat the parent's sum(n_c^2)/n; leaves
+// predict the majority class (lowest on ties); nodes in pre-order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <fstream>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kt_internal.hpp"
+
+namespace kt {
+
+typedef __int128 i128;
+
+static uint64_t isqrt_u64(uint64_t p) {
+  uint64_t r = (uint64_t)sqrtl((long double)p);
+  while ((i128)r * r > (i128)p) --r;
+  while ((i128)(r + 1) * (r + 1) <= (i128)p) ++r;
+  return r;
+}
+
+struct CartData {
+  std::vector<std::array<int64_t, 6>> X;
+  std::vector<int32_t> y;
+  int n_classes;
+  int max_depth;    // < 0: unlimited
+  int min_leaf;
+};
+
+static int32_t cart_build(const CartData& D, std::vector<int32_t>& idx, int depth, Tree& T) {
+  const int32_t node = (int32_t)T.feature.size();
+  T.feature.push_back(-1);
+  T.threshold.push_back(0);
+  T.left.push_back(-1);
+  T.right.push_back(-1);
+  T.cls.push_back(0);
+  const int nc = D.n_classes;
+  std::vector<int64_t> cnt(nc, 0);
+  for (int32_t i : idx) cnt[D.y[i]]++;
+  int best_c = 0;
+  for (int c = 1; c < nc; ++c) if (cnt[c] > cnt[best_c]) best_c = c;
+  T.cls[node] = best_c;
+  const int64_t n = (int64_t)idx.size();
+  int nonzero = 0;
+  for (int c = 0; c < nc; ++c) nonzero += cnt[c] > 0;
+  if (nonzero <= 1 || (D.max_depth >= 0 && depth >= D.max_depth) || n < 2 * (int64_t)D.min_leaf)
+    return node;
+  bool have = false;
+  i128 bnum = 0, bden = 1;
+  int bf = -1;
+  int64_t bt = 0;
+  std::vector<int32_t> order(idx);
+  std::vector<int64_t> cl(nc), cr(nc);
+  for (int f = 0; f < 6; ++f) {
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return D.X[a][f] < D.X[b][f]; });
+    std::fill(cl.begin(), cl.end(), 0);
+    cr = cnt;
+    int64_t pos = 0;
+    while (pos < n) {
+      const int64_t v = D.X[order[pos]][f];
+      while (pos < n && D.X[order[pos]][f] == v) {
+        cl[D.y[order[pos]]]++;
+        cr[D.y[order[pos]]]--;
+        ++pos;
+      }
+      if (pos == n) break;
+      const int64_t a = v, b = D.X[order[pos]][f];
+      const int64_t t = (int64_t)isqrt_u64((uint64_t)a * (uint64_t)b);
+      const int64_t nl = pos, nr = n - pos;
+      if (nl < D.min_leaf || nr < D.min_leaf) continue;
+      i128 A = 0, B = 0;
+      for (int c = 0; c < nc; ++c) { A += (i128)cl[c] * cl[c]; B += (i128)cr[c] * cr[c]; }
+      const i128 num = A * nr + B * nl, den = (i128)nl * nr;
+      if (!have || num * bden > bnum * den) {
+        have = true; bnum = num; bden = den; bf = f; bt = t;
+      }
+    }
+  }
+  if (!have) return node;
+  i128 P = 0;
+  for (int c = 0; c < nc; ++c) P += (i128)cnt[c] * cnt[c];
+  if (!(bnum * n > P * bden)) return node;
+  T.feature[node] = bf;
+  T.threshold[node] = bt;
+  std::vector<int32_t> li, ri;
+  for (int32_t i : idx) (D.X[i][bf] <= bt ? li : ri).push_back(i);
+  idx.clear();
+  idx.shrink_to_fit();
+  const int32_t l = cart_build(D, li, depth + 1, T);
+  T.left[node] = l;
+  const int32_t r = cart_build(D, ri, depth + 1, T);
+  T.right[node] = r;
+  return node;
+}
+
+static inline int64_t feat(const kt_shape& s, int f) {
+  switch (f) {
+    case 0: return s.M;
+    case 1: return s.N;
+    case 2: return s.K;
+    case 3: return s.batch;
+    case 4: return s.transA;
+    default: return s.transB;
+  }
+}
+
+static int32_t tree_walk(const Tree& T, const kt_shape& s) {
+  int32_t node = 0;
+  while (T.feature[node] >= 0)
+    node = feat(s, T.feature[node]) <= T.threshold[node] ? T.left[node] : T.right[node];
+  return T.cls[node];
+}
+
+// Device tree walk for a batch of shapes.  Layout of the packed buffer:
+// int64 threshold[n], int32 feature[n], left[n], right[n], cls[n], chosen[k].
+__global__ void select_tree_kernel(const kt_shape* __restrict__ shapes, int32_t n,
+                                   const char* __restrict__ tree, int32_t n_nodes, int32_t k,
+                                   int32_t* __restrict__ ids) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t* thr = (const int64_t*)tree;
+  const int32_t* fea = (const int32_t*)(thr + n_nodes);
+  const int32_t* lef = fea + n_nodes;
+  const int32_t* rig = lef + n_nodes;
+  const int32_t* cls = rig + n_nodes;
+  const int32_t* chosen = cls + n_nodes;
+  const kt_shape s = shapes[i];
+  int32_t node = 0;
+  for (int32_t step = 0; step < n_nodes && fea[node] >= 0; ++step) {
+    const int f = fea[node];
+    const int64_t x = f == 0 ? s.M : f == 1 ? s.N : f == 2 ? s.K : f == 3 ? s.batch
+                    : f == 4 ? (int64_t)s.transA : (int64_t)s.transB;
+    node = x <= thr[node] ? lef[node] : rig[node];
+  }
+  const int32_t c = cls[node];
+  ids[i] = (c >= 0 && c < k) ? chosen[c] : -1;
+}
+
+static kt_status upload_tree(Ctx* h) {
+  if (h->device < 0) return KT_OK;
+  if (h->d_tree) { (void)hipFree(h->d_tree); h->d_tree = nullptr; h->d_tree_bytes = 0; }
+  const size_t nn = h->tree.feature.size();
+  const size_t bytes = nn * 8 + nn * 4 * 4 + h->chosen.size() * 4;
+  std::vector<char> buf(bytes);
+  char* p = buf.data();
+  memcpy(p, h->tree.threshold.data(), nn * 8); p += nn * 8;
+  memcpy(p, h->tree.feature.data(), nn * 4); p += nn * 4;
+  memcpy(p, h->tree.left.data(), nn * 4); p += nn * 4;
+  memcpy(p, h->tree.right.data(), nn * 4); p += nn * 4;
+  memcpy(p, h->tree.cls.data(), nn * 4); p += nn * 4;
+  memcpy(p, h->chosen.data(), h->chosen.size() * 4);
+  hipError_t e = hipMalloc(&h->d_tree, bytes);
+  if (e != hipSuccess) { h->d_tree = nullptr; return hip_fail(h, e, "hipMalloc tree"); }
+  e = hipMemcpy(h->d_tree, buf.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "upload tree");
+  h->d_tree_bytes = bytes;
+  return KT_OK;
+}
+
+// Exhaustive selection: time every compiled configuration of the shape's
+// layout on handle-owned scratch operands; the fastest (lowest id on ties) is
+// cached for the shape.
+static kt_status exhaustive_select(Ctx* h, const kt_shape* s, int32_t* out) {
+  const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, h->sel_dtype};
+  auto it = h->exhaustive_cache.find(key);
+  if (it != h->exhaustive_cache.end()) { *out = it->second; return KT_OK; }
+  if (!need_device(h)) return KT_EINVAL;
+  const int dtype = h->sel_dtype;
+  const int64_t a_rows = s->transA ? s->K : s->M, a_cols = s->transA ? s->M : s->K;
+  const int64_t b_rows = s->transB ? s->N : s->K, b_cols = s->transB ? s->K : s->N;
+  const int64_t lda = std::max<int64_t>(a_cols, 1), ldb = std::max<int64_t>(b_cols, 1);
+  const int64_t ldc = std::max<int64_t>(s->N, 1);
+  const int64_t nA = s->batch * a_rows * lda, nB = s->batch * b_rows * ldb, nC = s->batch * s->M * ldc;
+  const size_t need = (size_t)(nA + nB + nC) * 4 + 1024;
+  if (h->scratch_bytes < need) {
+    if (h->scratch) (void)hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+    hipError_t e = hipMalloc(&h->scratch, need);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMalloc exhaustive-selection scratch");
+    h->scratch_bytes = need;
+  }
+  float* A = (float*)h->scratch;
+  float* B = A + ((nA + 63) & ~63LL);
+  float* C = B + ((nB + 63) & ~63LL);
+  hipError_t e = fill_uniform(A, nA, 1, 0, nullptr);
+  if (e == hipSuccess) e = fill_uniform(B, nB, 2, 0, nullptr);
+  if (e != hipSuccess) return hip_fail(h, e, "fill");
+  hipEvent_t e0, e1;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(h, e, "event");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(h, e, "event"); }
+  int32_t best = -1;
+  float best_ms = 0.f;
+  kt_status st = KT_OK;
+  for (int32_t id = 0; id < (int32_t)h->configs[dtype].size() && st == KT_OK; ++id) {
+    if (!find_launcher(h, dtype, id, s->transA, s->transB)) continue;
+    auto launch = [&]() {
+      return launch_gemm(h, dtype, s, 1.f, A, lda, a_rows * lda, B, ldb, b_rows * ldb, 0.f, C, ldc,
+                         s->M * ldc, nullptr, nullptr, id, nullptr);
+    };
+    if ((st = launch()) != KT_OK) break;
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < 3 && st == KT_OK; ++r) st = launch();
+    (void)hipEventRecord(e1, nullptr);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(h, e, "sync"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best < 0 || ms < best_ms) { best = id; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != KT_OK) return st;
+  if (best < 0) return fail(h, KT_EUNSUPPORTED, "no configuration compiled for this layout");
+  h->exhaustive_cache[key] = best;
+  *out = best;
+  return KT_OK;
+}
+
+kt_status select_config(Ctx* h, const kt_shape* s, int32_t* id) {
+  switch (h->sel_kind) {
+    case KT_SEL_DT_A:
+    case KT_SEL_DT_B:
+    case KT_SEL_DT_C: {
+      const int32_t c = tree_walk(h->tree, *s);
+      *id = h->chosen[c];
+      return KT_OK;
+    }
+    case KT_SEL_MLP:
+      return mlp_select_host(h, s, id);
+    case KT_SEL_EXHAUSTIVE:
+      return exhaustive_select(h, s, id);
+    default:
+      return fail(h, KT_ENOTFITTED, "no selector fitted or loaded");
+  }
+}
+
+}  // namespace kt
+
+using namespace kt;
+
+extern "C" {
+
+kt_status kt_fit_selector(kt_handle hh, kt_selector sel, const kt_shape* shapes,
+                          const int64_t* time_ns, int32_t n, int32_t d, const int32_t* chosen,
+                          int32_t k, const kt_mlp_opts* mlp, void* ws, size_t ws_bytes,
+                          void* stream) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (sel == KT_SEL_EXHAUSTIVE) {
+    h->sel_kind = KT_SEL_EXHAUSTIVE;
+    h->sel_dtype = KT_F32;
+    h->chosen.clear();
+    h->tree = Tree();
+    h->exhaustive_cache.clear();
+    return KT_OK;
+  }
+  if ((int)sel < 0 || (int)sel > KT_SEL_MLP) return fail(h, KT_EINVAL, "bad selector kind");
+  if (n < 1 || d < 1 || !shapes || !time_ns || !chosen || k < 1 || k > d)
+    return fail(h, KT_EINVAL, "bad training data");
+  for (int32_t j = 0; j < k; ++j) {
+    if (chosen[j] < 0 || chosen[j] >= d || chosen[j] >= (int32_t)h->configs[KT_F32].size())
+      return fail(h, KT_EINVAL, "chosen id out of range");
+    for (int32_t q = 0; q < j; ++q)
+      if (chosen[q] == chosen[j]) return fail(h, KT_EINVAL, "chosen ids must be distinct");
+  }
+  if (sel == KT_SEL_MLP) {
+    kt_status st = fit_mlp(h, shapes, time_ns, n, d, chosen, k, mlp, ws, ws_bytes, (hipStream_t)stream);
+    if (st != KT_OK) return st;
+    h->sel_kind = KT_SEL_MLP;
+    h->sel_dtype = KT_F32;
+    h->chosen.assign(chosen, chosen + k);
+    return KT_OK;
+  }
+  CartData D;
+  D.n_classes = k;
+  D.max_depth = sel == KT_SEL_DT_A ? -1 : sel == KT_SEL_DT_B ? 6 : 3;
+  D.min_leaf = sel == KT_SEL_DT_A ? 1 : sel == KT_SEL_DT_B ? 3 : 4;
+  D.X.resize(n);
+  D.y.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    for (int f = 0; f < 6; ++f) D.X[i][f] = feat(shapes[i], f);
+    // label: fastest chosen configuration, lowest position on equal times;
+    // non-positive (unmeasured) times never win
+    int32_t bj = 0;
+    int64_t bt = INT64_MAX;
+    for (int32_t j = 0; j < k; ++j) {
+      int64_t t = time_ns[(int64_t)i * d + chosen[j]];
+      if (t <= 0) t = INT64_MAX;
+      if (t < bt) { bt = t; bj = j; }
+    }
+    D.y[i] = bj;
+  }
+  Tree T;
+  std::vector<int32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  cart_build(D, idx, 0, T);
+  h->tree = std::move(T);
+  h->chosen.assign(chosen, chosen + k);
+  h->sel_kind = sel;
+  h->sel_dtype = KT_F32;
+  return upload_tree(h);
+}
+
+kt_status kt_select(kt_handle hh, const kt_shape* s, int32_t* config_id) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!s || !config_id) return fail(h, KT_EINVAL, "NULL argument");
+  if (s->M < 0 || s->N < 0 || s->K < 0 || s->batch < 0 || (s->transA & ~1) || (s->transB & ~1))
+    return fail(h, KT_EINVAL, "bad shape");
+  return select_config(h, s, config_id);
+}
+
+kt_status kt_select_batch(kt_handle hh, const kt_shape* d_shapes, int32_t n, int32_t* d_ids,
+                          void* stream) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!need_device(h)) return KT_EINVAL;
+  if (n < 0) return fail(h, KT_EINVAL, "n < 0");
+  if (n == 0) return KT_OK;
+  if (!d_shapes || !d_ids) return fail(h, KT_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  if (h->sel_kind >= KT_SEL_DT_A && h->sel_kind <= KT_SEL_DT_C) {
+    if (!h->d_tree) return fail(h, KT_ENOTFITTED, "tree not on the device");
+    hipLaunchKernelGGL(select_tree_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d_shapes, n,
+                       (const char*)h->d_tree, (int32_t)h->tree.feature.size(),
+                       (int32_t)h->chosen.size(), d_ids);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "select launch");
+    return KT_OK;
+  }
+  if (h->sel_kind == KT_SEL_MLP) {
+    return mlp_select_batch(h, d_shapes, n, d_ids, st);
+  }
+  if (h->sel_kind == KT_SEL_EXHAUSTIVE)
+    return fail(h, KT_EUNSUPPORTED, "exhaustive selection runs per shape on the host (kt_select)");
+  return fail(h, KT_ENOTFITTED, "no selector fitted or loaded");
+}
+
+kt_status kt_get_tree(kt_handle hh, int32_t* n_nodes, int32_t* feature, int64_t* threshold,
+                      int32_t* left, int32_t* right, int32_t* cls) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!n_nodes) return fail(h, KT_EINVAL, "NULL n_nodes");
+  if (h->sel_kind < KT_SEL_DT_A || h->sel_kind > KT_SEL_DT_C) return fail(h, KT_ENOTFITTED, "no tree fitted");
+  const size_t nn = h->tree.feature.size();
+  *n_nodes = (int32_t)nn;
+  if (feature) memcpy(feature, h->tree.feature.data(), nn * 4);
+  if (threshold) memcpy(threshold, h->tree.threshold.data(), nn * 8);
+  if (left) memcpy(left, h->tree.left.data(), nn * 4);
+  if (right) memcpy(right, h->tree.right.data(), nn * 4);
+  if (cls) memcpy(cls, h->tree.cls.data(), nn * 4);
+  return KT_OK;
+}
+
+// Text format:
+//   KTSEL 1
+//   kind <k> dtype <d>
+//   chosen <k> id...
+//   tree <n>          followed by n lines: feature threshold left right cls
+//   mlp <count>       followed by count floats in %a notation
+//   end
+kt_status kt_save(kt_handle hh, const char* path) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!path) return fail(h, KT_EINVAL, "NULL path");
+  if (h->sel_kind < 0) return fail(h, KT_ENOTFITTED, "nothing to save");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(h, KT_EIO, std::string("cannot write ") + path);
+  fprintf(f, "KTSEL 1\nkind %d dtype %d\nchosen %zu", h->sel_kind, h->sel_dtype, h->chosen.size());
+  for (int32_t c : h->chosen) fprintf(f, " %d", c);
+  fprintf(f, "\ntree %zu\n", h->tree.feature.size());
+  for (size_t i = 0; i < h->tree.feature.size(); ++i)
+    fprintf(f, "%d %lld %d %d %d\n", h->tree.feature[i], (long long)h->tree.threshold[i],
+            h->tree.left[i], h->tree.right[i], h->tree.cls[i]);
+  fprintf(f, "mlp %zu\n", h->mlp.params.size());
+  for (float v : h->mlp.params) fprintf(f, "%a\n", (double)v);
+  fprintf(f, "end\n");
+  const bool ok = fflush(f) == 0 && !ferror(f);
+  fclose(f);
+  if (!ok) return fail(h, KT_EIO, std::string("write error on ") + path);
+  return KT_OK;
+}
+
+kt_status kt_load(kt_handle hh, const char* path) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!path) return fail(h, KT_EINVAL, "NULL path");
+  std::ifstream in(path);
+  if (!in) return fail(h, KT_EIO, std::string("cannot read ") + path);
+  auto bad = [&](const char* why) { return fail(h, KT_EIO, std::string("malformed selector file: ") + why); };
+  std::string tag;
+  int ver = 0, kind = -1, dtype = -1;
+  if (!(in >> tag >> ver) || tag != "KTSEL" || ver != 1) return bad("header");
+  if (!(in >> tag >> kind) || tag != "kind" || kind < KT_SEL_DT_A || kind > KT_SEL_EXHAUSTIVE) return bad("kind");
+  if (!(in >> tag >> dtype) || tag != "dtype" || dtype != KT_F32) return bad("dtype");
+  size_t k = 0;
+  if (!(in >> tag >> k) || tag != "chosen" || k > 4096) return bad("chosen");
+  std::vector<int32_t> chosen(k);
+  for (size_t j = 0; j < k; ++j)
+    if (!(in >> chosen[j]) || chosen[j] < 0 || chosen[j] >= (int32_t)h->configs[KT_F32].size()) return bad("chosen id");
+  size_t nn = 0;
+  if (!(in >> tag >> nn) || tag != "tree" || nn > (1u << 24)) return bad("tree");
+  Tree T;
+  T.feature.resize(nn); T.threshold.resize(nn); T.left.resize(nn); T.right.resize(nn); T.cls.resize(nn);
+  for (size_t i = 0; i < nn; ++i) {
+    long long thr;
+    if (!(in >> T.feature[i] >> thr >> T.left[i] >> T.right[i] >> T.cls[i])) return bad("tree node");
+    T.threshold[i] = thr;
+    if (T.feature[i] < -1 || T.feature[i] > 5) return bad("feature");
+    if (T.feature[i] >= 0 && (T.left[i] <= (int32_t)i || T.right[i] <= (int32_t)i ||
+                              T.left[i] >= (int32_t)nn || T.right[i] >= (int32_t)nn))
+      return bad("child index");
+    if (T.cls[i] < 0 || T.cls[i] >= (int32_t)std::max<size_t>(k, 1)) return bad("class");
+  }
+  size_t np = 0;
+  if (!(in >> tag >> np) || tag != "mlp" || np > (1u << 24)) return bad("mlp");
+  std::vector<float> params(np);
+  for (size_t i = 0; i < np; ++i) {
+    std::string tok;
+    if (!(in >> tok)) return bad("mlp value");
+    char* endp = nullptr;
+    const double v = strtod(tok.c_str(), &endp);
+    if (!endp || *endp) return bad("mlp value");
+    params[i] = (float)v;
+  }
+  if (!(in >> tag) || tag != "end") return bad("end");
+  if (kind <= KT_SEL_DT_C && (nn == 0 || k == 0)) return bad("tree selector without nodes");
+  if (kind == KT_SEL_MLP) {
+    const size_t want = (size_t)64 * 6 + 64 + 64 * 64 + 64 + k * 64 + k;
+    if (np != want) return bad("mlp size");
+  }
+  h->sel_kind = kind;
+  h->sel_dtype = dtype;
+  h->chosen = chosen;
+  h->tree = std::move(T);
+  h->mlp.k = (int32_t)k;
+  h->mlp.params = std::move(params);
+  h->exhaustive_cache.clear();
+  if (kind <= KT_SEL_DT_C) return upload_tree(h);
+  if (kind == KT_SEL_MLP) {
+    return mlp_upload(h);
+  }
+  return KT_OK;
+}
+
+}  // extern "C"
