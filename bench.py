@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Benchmark of the deployed, pruned and selected FP32 GEMM library on MI355X.
+
+Workload (one "step"): the 1200 GEMM problems of the sweep set -- 300 seeded
+log-uniform (M, N, K, batch) shapes, M, N, K in 16..4096 and batch in 1..64,
+each in the four transpose layouts -- run once each through the library's
+deployed path: kt_gemm with config_id = -1, so the fitted selector (a
+decision tree over the k kernels chosen by k-means pruning of the benchmark
+table) picks the configuration and the chosen kernel is launched.  Operands
+live in HBM before timing starts.
+
+Setup (untimed, reported): the benchmark table of every configuration on
+every problem (the sweep, sections 3 and 3.1 of the paper) is loaded from
+the committed dataset; k-means pruning runs on the GPU over the training
+problems (section 4); the decision trees A/B/C and the MLP cost model are
+fitted on the training problems (section 5.1) and evaluated on the held-out
+test problems against exhaustive search (section 4.3).
+
+Prints one JSON line.  Only one GPU is supported: --gpus N > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+SEL_NAMES = {0: "DT-A", 1: "DT-B", 2: "DT-C", 3: "MLP"}
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _geomean(x):
+    x = np.asarray(x, dtype=np.float64)
+    return float(math.exp(np.mean(np.log(x))))
+
+
+def cpu_baseline(problems, budget_s=15.0, seed=13145):
+    """The FP64 CPU oracle (test infrastructure) timed on a bounded, seeded
+    sample of the same problem set: problems are taken in a fixed seeded order
+    (those up to 2 GFLOP each) until the time budget is spent."""
+    import synth
+    from oracle import gemm as og
+    rng = np.random.default_rng(seed)
+    small = [p for p in problems if 2 * p[0] * p[1] * p[2] * p[3] <= 2e9]
+    order = rng.permutation(len(small))
+    flops, t_tot, n = 0.0, 0.0, 0
+    for i in order:
+        M, N, K, b, ta, tb = small[i]
+        a = synth.uniform_operand(synth.operand_seed(n, 0), b * M * K)
+        bb = synth.uniform_operand(synth.operand_seed(n, 1), b * K * N)
+        lda = M if ta else K
+        ldb = K if tb else N
+        t0 = time.perf_counter()
+        og.gemm(M, N, K, b, ta, tb, 1.0, 0.0, a, lda, M * K, bb, ldb, K * N)
+        t_tot += time.perf_counter() - t0
+        flops += 2.0 * M * N * K * b
+        n += 1
+        if t_tot >= budget_s:
+            break
+    return dict(value=round(flops / t_tot / 1e12, 6), unit="TFLOP/s", cores=og.max_threads(),
+                kind="oracle",
+                sample=f"{n} problems of the 1200-problem set (seeded order, each <= 2 GFLOP), "
+                       f"{flops / 1e9:.1f} GFLOP in {t_tot:.1f} s, FP64 triple loop")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--selector", default="DT-B", choices=["DT-A", "DT-B", "DT-C", "MLP"])
+    ap.add_argument("--table", default=None)
+    ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
+              "design is described in DESIGN.md and not built", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2008_13145_amd as kt
+    import synth
+    from paper_2008_13145_amd import tune
+
+    table_path = a.table or tune.DEFAULT_TABLE
+    if not os.path.exists(table_path):
+        raise SystemExit(f"benchmark table {table_path} missing: run "
+                         "`python -m paper_2008_13145_amd.tune sweep` on the GPU first")
+    T, P, C, meta = tune.load_table(table_path)
+    problems = [tuple(int(v) for v in p) for p in P]
+    if not (T >= 0).all():
+        raise SystemExit("benchmark table is incomplete; resume the sweep")
+    n_prob, n_cfg = T.shape
+    train, test = synth.train_test_split()
+    tr_rows = synth.rows_of_shapes(train)
+    te_rows = synth.rows_of_shapes(test)
+
+    h = kt.Handle(0)
+    assert [tuple(c) for c in C.tolist()] == h.configs()
+    stream = torch.cuda.current_stream()
+
+    # ---- pruning (GPU k-means on the training rows) and the Top-N baseline
+    k = a.k
+    ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), n_cfg, max(k, 15), 10)
+    pws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pr = h.prune(T[tr_rows], k, norm=kt.NORM_RELATIVE, seed=synth.SEED, n_init=10, max_iter=300,
+                 workspace=pws, ws_bytes=ws_bytes, stream=stream)
+    prune_ms = (time.perf_counter() - t0) * 1e3
+    chosen = pr["chosen"]
+    topn = h.prune_topn(T[tr_rows], k, workspace=pws, ws_bytes=ws_bytes, stream=stream)
+
+    t_best = T.min(axis=1)
+
+    def ratios(rows, picks):
+        return t_best[rows] / T[rows, picks]
+
+    evals = {}
+    ceil_te = ratios(te_rows, [chosen[int(np.argmin(T[r, chosen]))] for r in te_rows])
+    topn_te = ratios(te_rows, [topn[int(np.argmin(T[r, topn]))] for r in te_rows])
+    evals["kmeans_ceiling"] = _geomean(ceil_te)
+    evals["topn_ceiling"] = _geomean(topn_te)
+    # single best kernel over the training rows (no selector at all)
+    single = int(np.argmax(np.exp(np.mean(np.log(t_best[tr_rows, None] / T[tr_rows]), axis=0))))
+    evals["single_kernel"] = _geomean(ratios(te_rows, [single] * len(te_rows)))
+
+    # ---- selectors fitted on the training rows
+    tr_shapes = [problems[r] for r in tr_rows]
+    fit_ms = {}
+    mws_bytes = kt.Handle.mlp_workspace_bytes(len(tr_rows), n_cfg, k)
+    mws = torch.empty(mws_bytes, dtype=torch.uint8, device="cuda")
+    for kind in (0, 1, 2, 3):
+        t0 = time.perf_counter()
+        h.fit_selector(kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
+                       workspace=mws, ws_bytes=mws_bytes, stream=stream)
+        torch.cuda.synchronize()
+        fit_ms[SEL_NAMES[kind]] = (time.perf_counter() - t0) * 1e3
+        picks = [h.select(*problems[r]) for r in te_rows]
+        evals[SEL_NAMES[kind]] = _geomean(ratios(te_rows, picks))
+    sel_kind = {v: kk for kk, v in SEL_NAMES.items()}[a.selector]
+    h.fit_selector(sel_kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
+                   workspace=mws, ws_bytes=mws_bytes, stream=stream)
+    torch.cuda.synchronize()
+    picks_all = [h.select(*p) for p in problems]
+    t0 = time.perf_counter()
+    for _ in range(5):
+        for p in problems:
+            h.select(*p)
+    select_us = (time.perf_counter() - t0) / (5 * n_prob) * 1e6
+    sel_all = _geomean(ratios(list(range(n_prob)), picks_all))
+
+    # ---- operands resident in HBM: one pool sized for the largest problem
+    ws_all = kt.Handle.sweep_workspace_bytes(problems)
+    pool = torch.empty(ws_all // 4 + 64, dtype=torch.float32, device="cuda")
+    h.fill_uniform(pool, pool.numel(), synth.operand_seed(synth.SEED, 0), stream=stream)
+    base = pool.data_ptr()
+    plans = []
+    for (M, N, K, b, ta, tb) in problems:
+        lda = M if ta else K
+        ldb = K if tb else N
+        sA, sB, sC = M * K, K * N, M * N
+        offB = ((b * sA * 4 + 255) // 256) * 256
+        offC = offB + ((b * sB * 4 + 255) // 256) * 256
+        plans.append((kt.shape(M, N, K, b, ta, tb), base, lda, sA, base + offB, ldb, sB,
+                      base + offC, N, sC))
+    flops = np.array([2.0 * p[0] * p[1] * p[2] * p[3] for p in problems])
+    total_flops = float(flops.sum())
+
+    def step(events=None):
+        for i, pl in enumerate(plans):
+            if events is not None:
+                events[i][0].record(stream)
+            h.gemm_raw(kt.F32, pl[0], 1.0, pl[1], pl[2], pl[3], pl[4], pl[5], pl[6], 0.0, pl[7],
+                       pl[8], pl[9], config_id=-1, stream=stream)
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in problems] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(a.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / a.steps
+    per_launch = np.array([[evs[s][i][0].elapsed_time(evs[s][i][1]) for i in range(n_prob)]
+                           for s in range(a.steps)])          # ms
+    t_launch = per_launch.mean(axis=0)
+    value = total_flops / (ms_per_step * 1e-3) / 1e12
+
+    # dominant kernel: the (configuration, layout) instantiation with the most time
+    cfgs = h.configs()
+    inst_time = {}
+    for i, p in enumerate(problems):
+        key = (picks_all[i], p[4], p[5])
+        inst_time[key] = inst_time.get(key, 0.0) + t_launch[i]
+    dom = max(inst_time, key=inst_time.get)
+    dom_rows = [i for i, p in enumerate(problems) if (picks_all[i], p[4], p[5]) == dom]
+    dom_flops = float(flops[dom_rows].sum())
+    dom_ms = float(t_launch[dom_rows].sum())
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    bm, bn, tt, bk = cfgs[dom[0]]
+    dom_name = f"gemm_f32_kernel<{bm}, {bn}, {tt}, {bk}, {dom[1]}, {dom[2]}>"
+
+    # exhaustive-best comparison: live launch times vs the table's best
+    pct_exh_live = float(t_best.sum() * 1e-6 / t_launch.sum())
+    out = {
+        "metric": "GEMM TFLOP/s; % of exhaustive-best config; % MFMA peak; selector regret",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sweep set: 300 seeded log-uniform (M,N,K in 16..4096, batch 1..64) x 4 "
+                        "layouts = 1200 FP32 GEMMs, alpha 1, beta 0; each run through the "
+                        f"deployed path (selector {a.selector} over k={k} k-means-pruned kernels)",
+            "problems": n_prob, "gflop_per_step": round(total_flops / 1e9, 3),
+            "k": k, "selector": a.selector, "chosen": [list(cfgs[c]) for c in chosen],
+            "train_test_shapes": [len(train), len(test)],
+        },
+        "pct_mfma_peak": round(100 * value / FP32_PEAK_TFLOPS, 2),
+        "pct_of_exhaustive_best": {
+            "time_weighted_live": round(100 * pct_exh_live, 2),
+            "geomean_all_rows_table": round(100 * sel_all, 2),
+        },
+        "selector_pct_of_optimal_test": {kk: round(100 * v, 2) for kk, v in evals.items()},
+        "selector_regret_test": {kk: round(1 - v, 4) for kk, v in evals.items()},
+        "select_us_per_call": round(select_us, 3),
+        "prune_ms_gpu": round(prune_ms, 2),
+        "fit_ms": {kk: round(v, 1) for kk, v in fit_ms.items()},
+        "roofline": {
+            "bound": "mfma", "kernel": dom_name, "launches_per_step": len(dom_rows),
+            "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel_ms_per_step": round(dom_ms, 3),
+        },
+        "table": {"path": os.path.relpath(table_path, ROOT), "device": meta.get("device"),
+                  "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problems, a.cpu_budget_s)
+    h.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -99,10 +99,13 @@ int32_t kt_abi_version(void);
 
 /* ------------------------------------------------------ configuration space */
 
-/* Number of tile configurations compiled for a dtype (per layout).
- * For KT_F32 the full space of section 3's kernel re-designed for MFMA:
- * bm, bn in {8,16,32,64,128}, t in {1,2,4,8}, bk in {8,16,32,64}, with bm and bn
- * multiples of 8t and 1..16 waves per work-group: 164 configurations. */
+/* Number of tile configurations of a dtype (per layout; a deploy build may
+ * compile only some of them, see kt_config_compiled).
+ * KT_F32: the space of section 3's kernel re-designed for MFMA: bm, bn in
+ * {8,16,32,64,128}, t in {1,2,4,8}, bk in {8,16,32,64}, with bm and bn
+ * multiples of 8t and 1..16 waves per work-group: 164 configurations.
+ * KT_BF16 / KT_FP8E4M3: bm, bn in {32,64,128,256}, t in {4,8}, bk in
+ * {32,64,128}, 1..16 waves, LDS stages within 160 KiB: 59 configurations. */
 kt_status kt_num_configs(kt_handle h, kt_dtype dtype, int32_t* n);
 /* Configuration `id` (0 <= id < n) of a dtype.  KT_EINVAL if out of range. */
 kt_status kt_get_config(kt_handle h, kt_dtype dtype, int32_t id, kt_config* out);
@@ -120,7 +123,8 @@ kt_status kt_config_compiled(kt_handle h, kt_dtype dtype, int32_t id, int32_t tr
  * config_id >= 0 forces that configuration; -1 asks the fitted selector.
  * With beta == 0, C is never read (NaN in C does not propagate).  M, N or
  * batch == 0 is a no-op; K == 0 gives C = beta * C.  Unaligned pointers or
- * leading dimensions take a scalar-load path; they are never an error. */
+ * leading dimensions are never an error (FP32 rows load as dword-aligned
+ * 16-byte vectors whatever the leading dimension). */
 kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha,
                   const void* A, int64_t lda, int64_t strideA,
                   const void* B, int64_t ldb, int64_t strideB,
@@ -133,6 +137,18 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
  * values in [-1, 1) exact in FP32. */
 kt_status kt_fill_uniform(kt_handle h, float* dst, int64_t n, uint64_t seed, int64_t offset,
                           void* stream);
+
+/* Convert n FP32 values (device) to BF16 bit patterns (device uint16),
+ * round to nearest even, NaN kept quiet.  Asynchronous on `stream`. */
+kt_status kt_convert_bf16(kt_handle h, const float* x, int64_t n, uint16_t* y, void* stream);
+
+/* Per-tensor FP8-e4m3 quantization of n FP32 values (device): s = 448 / amax
+ * (FP32, s = 1 when every value is 0) is written to d_scale[0] (device) and
+ * y[i] = e4m3(x[i] * s) (OCP e4m3fn codes, round to nearest even, saturating
+ * at +-448, NaN -> 0x7F).  Dequantized value = decode(y) / s.  The workspace
+ * (device, >= 4 bytes) holds the running amax.  Asynchronous on `stream`. */
+kt_status kt_quantize_fp8(kt_handle h, const float* x, int64_t n, uint8_t* y, float* d_scale,
+                          void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ sweep */
 
@@ -248,6 +264,56 @@ kt_status kt_get_tree(kt_handle h, int32_t* n_nodes, int32_t* feature, int64_t* 
  * file and leaves the handle unchanged in that case. */
 kt_status kt_save(kt_handle h, const char* path);
 kt_status kt_load(kt_handle h, const char* path);
+
+/* ------------------------------------------------- grouped GEMM (BF16) */
+
+/* A batch of uneven GEMMs C_i = alpha * A_i * B_i + beta * C_i (BF16 A_i row-
+ * major M x K, BF16 B_i row-major K x N, FP32 C_i row-major M x N; members
+ * must have batch 1 and no transposes) run by one persistent kernel: the
+ * members' output tiles form one work list that resident work-groups walk.
+ * The kernel is captured with its setup in a hipGraph; one plan = one graph
+ * launch per run. */
+typedef struct {
+  int32_t config_id;     /* BF16 tile configuration (kt_get_config(KT_BF16, id)) */
+  int32_t schedule;      /* 0: static round robin over work-groups; 1: atomic work counter */
+  int32_t order;         /* 0: members in the given order; 1: largest K first */
+  int32_t wgs_per_cu;    /* persistent work-groups per compute unit (1..4) */
+  uint32_t* visits;      /* optional device counters [n_work]: each work item adds 1 (tests) */
+} kt_grouped_opts;
+
+typedef struct kt_grouped_plan_s* kt_grouped_plan;
+
+/* Device workspace for a group (descriptors, work list, counter). */
+kt_status kt_grouped_workspace_bytes(const kt_shape* shapes, int32_t n, size_t* bytes);
+/* Number of tile configurations the grouped kernel is compiled for. */
+kt_status kt_grouped_num_candidates(int32_t* n);
+/* Build a plan: uploads descriptors and the work list into the workspace
+ * (which must stay untouched while the plan lives) and captures the graph.
+ * A, B, C are host arrays of n device pointers.  opts NULL = the options the
+ * autotuner found on this handle, else a default.  Synchronizes `stream`. */
+kt_status kt_grouped_plan_create(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                                 const void* const* A, const void* const* B, float* const* C,
+                                 float alpha, float beta, const kt_grouped_opts* opts,
+                                 void* workspace, size_t ws_bytes, void* stream,
+                                 kt_grouped_plan* out);
+/* One graph launch of the plan on `stream` (asynchronous). */
+kt_status kt_grouped_plan_launch(kt_handle h, kt_grouped_plan plan, void* stream);
+/* Work-list length and options of a plan. */
+kt_status kt_grouped_plan_info(kt_grouped_plan plan, int32_t* n_work, kt_grouped_opts* opts);
+kt_status kt_grouped_plan_destroy(kt_grouped_plan plan);
+/* Plan, launch once, synchronize, destroy. */
+kt_status kt_grouped_gemm(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                          const void* const* A, const void* const* B, float* const* C, float alpha,
+                          float beta, const kt_grouped_opts* opts, void* workspace, size_t ws_bytes,
+                          void* stream);
+/* The library's autotuner: successive halving over (tile configuration,
+ * schedule, order, work-groups per CU), timing whole graph launches of the
+ * real group (C is overwritten with alpha = 1, beta = 0).  The winner is
+ * returned and kept on the handle as the default for later plans. */
+kt_status kt_autotune_grouped(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                              const void* const* A, const void* const* B, float* const* C,
+                              void* workspace, size_t ws_bytes, void* stream,
+                              kt_grouped_opts* best, float* best_ms, int32_t* evaluations);
 
 /* ------------------------------------------------------- MLP cost model */
 

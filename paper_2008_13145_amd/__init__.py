@@ -50,6 +50,11 @@ class MlpOpts(ctypes.Structure):
                 ("graph_steps", c_i32)]
 
 
+class GroupedOpts(ctypes.Structure):
+    _fields_ = [("config_id", c_i32), ("schedule", c_i32), ("order", c_i32), ("wgs_per_cu", c_i32),
+                ("visits", c_vp)]
+
+
 class KtError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -68,6 +73,8 @@ _SIGS = {
     "kt_gemm": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_f32, c_vp, c_i64, c_i64, c_vp, c_i64,
                         c_i64, c_f32, c_vp, c_i64, c_i64, c_vp, c_vp, c_i32, c_vp]),
     "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
+    "kt_convert_bf16": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "kt_quantize_fp8": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "kt_sweep_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_sweep": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_i32,
                          ctypes.POINTER(SweepOpts), c_vp, c_sz, c_vp, c_vp]),
@@ -83,6 +90,19 @@ _SIGS = {
     "kt_get_tree": (c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp]),
     "kt_save": (c_i32, [c_vp, ctypes.c_char_p]),
     "kt_load": (c_i32, [c_vp, ctypes.c_char_p]),
+    "kt_grouped_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
+    "kt_grouped_num_candidates": (c_i32, [ctypes.POINTER(c_i32)]),
+    "kt_grouped_plan_create": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp,
+                                       c_f32, c_f32, ctypes.POINTER(GroupedOpts), c_vp, c_sz, c_vp,
+                                       ctypes.POINTER(c_vp)]),
+    "kt_grouped_plan_launch": (c_i32, [c_vp, c_vp, c_vp]),
+    "kt_grouped_plan_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(GroupedOpts)]),
+    "kt_grouped_plan_destroy": (c_i32, [c_vp]),
+    "kt_grouped_gemm": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp, c_f32,
+                                c_f32, ctypes.POINTER(GroupedOpts), c_vp, c_sz, c_vp]),
+    "kt_autotune_grouped": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp, c_vp,
+                                    c_sz, c_vp, ctypes.POINTER(GroupedOpts), ctypes.POINTER(c_f32),
+                                    ctypes.POINTER(c_i32)]),
     "kt_mlp_workspace_bytes": (c_i32, [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_mlp_num_params": (c_i32, [c_i32, ctypes.POINTER(c_i32)]),
     "kt_mlp_features": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
@@ -236,6 +256,13 @@ class Handle:
         self._check(self.L.kt_fill_uniform(self.h, _ptr(dst), int(n), int(seed) & (2 ** 64 - 1),
                                            int(offset), _stream(stream)))
 
+    def convert_bf16(self, x, n, y, stream=None):
+        self._check(self.L.kt_convert_bf16(self.h, _ptr(x), int(n), _ptr(y), _stream(stream)))
+
+    def quantize_fp8(self, x, n, y, d_scale, workspace, ws_bytes=16, stream=None):
+        self._check(self.L.kt_quantize_fp8(self.h, _ptr(x), int(n), _ptr(y), _ptr(d_scale),
+                                           _ptr(workspace), int(ws_bytes), _stream(stream)))
+
     # -------------------------------------------------------------- sweep
     @staticmethod
     def sweep_workspace_bytes(shapes, dtype=F32) -> int:
@@ -385,3 +412,59 @@ class Handle:
         out = np.zeros(n.value, dtype=np.float32)
         self._check(self.L.kt_get_mlp(self.h, ctypes.byref(n), out.ctypes.data))
         return out
+
+    # ------------------------------------------------------------ grouped
+    @staticmethod
+    def grouped_workspace_bytes(shapes) -> int:
+        arr = shapes_array(shapes)
+        b = c_sz()
+        st = lib().kt_grouped_workspace_bytes(arr, len(shapes), ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "grouped workspace query")
+        return b.value
+
+    @staticmethod
+    def _ptr_array(ptrs):
+        arr = (c_vp * max(1, len(ptrs)))()
+        for i, p in enumerate(ptrs):
+            arr[i] = _ptr(p)
+        return arr
+
+    def grouped_plan(self, shapes, A, B, C, alpha=1.0, beta=0.0, opts=None, workspace=None,
+                     ws_bytes=0, dtype=BF16, stream=None):
+        """shapes: list of (M, N, K); A, B, C: lists of device buffers."""
+        arr = shapes_array([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
+        plan = c_vp()
+        o = None
+        if opts is not None:
+            o = opts if isinstance(opts, GroupedOpts) else GroupedOpts(*opts)
+        self._check(self.L.kt_grouped_plan_create(
+            self.h, dtype, arr, len(shapes), self._ptr_array(A), self._ptr_array(B),
+            self._ptr_array(C), float(alpha), float(beta), None if o is None else ctypes.byref(o),
+            _ptr(workspace), int(ws_bytes), _stream(stream), ctypes.byref(plan)))
+        return plan
+
+    def grouped_launch(self, plan, stream=None):
+        self._check(self.L.kt_grouped_plan_launch(self.h, plan, _stream(stream)))
+
+    def grouped_info(self, plan):
+        n = c_i32()
+        o = GroupedOpts()
+        st = self.L.kt_grouped_plan_info(plan, ctypes.byref(n), ctypes.byref(o))
+        if st != 0:
+            raise KtError(st, "plan info")
+        return n.value, (o.config_id, o.schedule, o.order, o.wgs_per_cu)
+
+    def grouped_destroy(self, plan):
+        self.L.kt_grouped_plan_destroy(plan)
+
+    def autotune_grouped(self, shapes, A, B, C, workspace, ws_bytes, dtype=BF16, stream=None):
+        arr = shapes_array([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
+        o = GroupedOpts()
+        ms = c_f32()
+        ev = c_i32()
+        self._check(self.L.kt_autotune_grouped(
+            self.h, dtype, arr, len(shapes), self._ptr_array(A), self._ptr_array(B),
+            self._ptr_array(C), _ptr(workspace), int(ws_bytes), _stream(stream), ctypes.byref(o),
+            ctypes.byref(ms), ctypes.byref(ev)))
+        return (o.config_id, o.schedule, o.order, o.wgs_per_cu), ms.value, ev.value

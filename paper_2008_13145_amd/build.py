@@ -52,15 +52,15 @@ def _compile(src, obj, verbose):
     return obj
 
 
-def build(jobs: int | None = None, f32_ids=None, out: str = LIB, verbose: bool = False,
-          tag: str = "full") -> str:
+def build(jobs: int | None = None, f32_ids=None, lp_ids=None, out: str = LIB,
+          verbose: bool = False, tag: str = "full") -> str:
     """Compile and link; returns the path of the shared library."""
     from . import codegen
     bdir = os.path.join(HERE, "_build", tag)
     gdir = os.path.join(bdir, "gen")
     odir = os.path.join(bdir, "obj")
     os.makedirs(odir, exist_ok=True)
-    gen = codegen.generate(gdir, f32_ids=f32_ids)
+    gen = codegen.generate(gdir, f32_ids=f32_ids, lp_ids=lp_ids)
     srcs = _sources() + gen
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = [os.path.join(odir, os.path.basename(s) + ".o") for s in srcs]
@@ -78,15 +78,32 @@ def build(jobs: int | None = None, f32_ids=None, out: str = LIB, verbose: bool =
     return out
 
 
+def build_deploy(jobs: int | None = None, verbose: bool = False):
+    """Deploy build from the recorded k-means choice (data/deploy_f32.json):
+    only the chosen FP32 configurations, in all four layouts.  Returns the
+    library path, or None when no choice has been recorded."""
+    import json
+    spec_path = os.path.join(HERE, "data", "deploy_f32.json")
+    if not os.path.exists(spec_path):
+        return None
+    spec = json.load(open(spec_path))
+    return build(jobs=jobs, f32_ids=spec["chosen"], lp_ids=[],
+                 out=os.path.join(HERE, "libkt_deploy.so"), verbose=verbose, tag="deploy")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--ids", type=str, default=None, help="comma-separated FP32 config ids (deploy build)")
     ap.add_argument("--out", type=str, default=None)
+    ap.add_argument("--deploy", action="store_true", help="also build the recorded deploy library")
     a = ap.parse_args(argv)
     ids = None if a.ids is None else [int(x) for x in a.ids.split(",") if x]
     out = a.out or (LIB if ids is None else os.path.join(HERE, "libkt_deploy.so"))
-    build(jobs=a.jobs, f32_ids=ids, out=out, verbose=True, tag="full" if ids is None else "deploy")
+    build(jobs=a.jobs, f32_ids=ids, lp_ids=None if ids is None else [], out=out, verbose=True,
+          tag="full" if ids is None else "deploy")
+    if a.deploy and ids is None:
+        build_deploy(jobs=a.jobs, verbose=True)
 
 
 if __name__ == "__main__":

@@ -40,49 +40,92 @@ def f32_configs():
     return out
 
 
+LP_TILES = (32, 64, 128, 256)
+LP_THREAD_TILES = (4, 8)
+LP_K_TILES = (32, 64, 128)
+
+
+def lp_configs():
+    """Ordered (bm, bn, t, bk) list shared by the BF16 and FP8 families: wave
+    blocks of 32x32 (t = 4) or 64x64 (t = 8) MFMA outputs, 1..16 waves, and
+    double-buffered LDS stages (rows padded by 16 bytes) within 160 KiB at
+    two bytes per element."""
+    out = []
+    for t in LP_THREAD_TILES:
+        wt = 8 * t
+        for bm in LP_TILES:
+            for bn in LP_TILES:
+                if bm % wt or bn % wt:
+                    continue
+                waves = (bm * bn) // (wt * wt)
+                if not 1 <= waves <= 16:
+                    continue
+                for bk in LP_K_TILES:
+                    if 2 * (bm + bn) * (bk + 8) * 2 > 160 * 1024:
+                        continue
+                    out.append((bm, bn, t, bk))
+    return out
+
+
+DTYPES = (  # (name, config list, launcher template)
+    ("f32", f32_configs, "launch_gemm_f32<{bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_f32.hpp"),
+    ("bf16", lp_configs, "launch_gemm_lp<2, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
+    ("fp8", lp_configs, "launch_gemm_lp<1, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
+)
+
+
 def _chunks(seq, n):
     size = (len(seq) + n - 1) // n
     return [seq[i:i + size] for i in range(0, len(seq), size)]
 
 
-def generate(out_dir: str, f32_ids=None, n_parts: int = 24):
-    """Write the generated sources; return the list of .hip/.cpp paths."""
+def generate(out_dir: str, f32_ids=None, lp_ids=None, n_parts: int = 24, lp_parts: int = 12):
+    """Write the generated sources; return the list of .hip/.cpp paths.
+    f32_ids / lp_ids restrict the instantiated configurations (deploy build);
+    None means all."""
     os.makedirs(out_dir, exist_ok=True)
-    cfgs = f32_configs()
-    ids = list(range(len(cfgs))) if f32_ids is None else sorted(set(int(i) for i in f32_ids))
-    insts = [(i, ta, tb) for i in ids for (ta, tb) in LAYOUTS]
-    parts = _chunks(insts, max(1, min(n_parts, len(insts)))) if insts else []
     paths = []
-    for p, chunk in enumerate(parts):
-        lines = ['#include "gemm_f32.hpp"', '#include "registry.hpp"', "", "namespace kt {",
-                 f"extern LaunchEntry f32_part{p}[] = {{"]
-        for (i, ta, tb) in chunk:
-            bm, bn, t, bk = cfgs[i]
-            lines.append(f"  {{{i}, {ta}, {tb}, &launch_gemm_f32<{bm}, {bn}, {t}, {bk}, {ta}, {tb}>}},")
-        lines += ["};", f"extern const int f32_part{p}_n = {len(chunk)};", "}  // namespace kt", ""]
-        path = os.path.join(out_dir, f"f32_part{p}.hip")
-        _write_if_changed(path, "\n".join(lines))
-        paths.append(path)
-    # configuration table + registry index
-    lines = ['#include "registry.hpp"', "", "namespace kt {"]
-    for p in range(len(parts)):
-        lines.append(f"extern LaunchEntry f32_part{p}[];")
-        lines.append(f"extern const int f32_part{p}_n;")
-    lines.append("const ConfigDef f32_config_table[] = {")
-    for (bm, bn, t, bk) in cfgs:
-        lines.append(f"  {{{bm}, {bn}, {t}, {bk}}},")
-    lines.append("};")
-    lines.append(f"const int f32_config_count = {len(cfgs)};")
-    lines.append("const PartRef f32_parts[] = {")
-    for p in range(len(parts)):
-        lines.append(f"  {{f32_part{p}, &f32_part{p}_n}},")
-    if not parts:
-        lines.append("  {nullptr, nullptr},")
-    lines.append("};")
-    lines.append(f"const int f32_part_count = {len(parts)};")
-    lines += ["}  // namespace kt", ""]
+    reg = ['#include "registry.hpp"', "", "namespace kt {"]
+    tables = []
+    for (name, cfg_fn, tmpl, header) in DTYPES:
+        cfgs = cfg_fn()
+        sel = f32_ids if name == "f32" else lp_ids
+        ids = list(range(len(cfgs))) if sel is None else sorted(set(int(i) for i in sel))
+        insts = [(i, ta, tb) for i in ids for (ta, tb) in LAYOUTS]
+        nparts = n_parts if name == "f32" else lp_parts
+        parts = _chunks(insts, max(1, min(nparts, len(insts)))) if insts else []
+        for p, chunk in enumerate(parts):
+            lines = [f'#include "{header}"', '#include "registry.hpp"', "", "namespace kt {",
+                     f"extern LaunchEntry {name}_part{p}[] = {{"]
+            for (i, ta, tb) in chunk:
+                bm, bn, t, bk = cfgs[i]
+                fn = tmpl.format(bm=bm, bn=bn, t=t, bk=bk, ta=ta, tb=tb)
+                lines.append(f"  {{{i}, {ta}, {tb}, &{fn}}},")
+            lines += ["};", f"extern const int {name}_part{p}_n = {len(chunk)};",
+                      "}  // namespace kt", ""]
+            path = os.path.join(out_dir, f"{name}_part{p}.hip")
+            _write_if_changed(path, "\n".join(lines))
+            paths.append(path)
+        for p in range(len(parts)):
+            reg.append(f"extern LaunchEntry {name}_part{p}[];")
+            reg.append(f"extern const int {name}_part{p}_n;")
+        reg.append(f"static const ConfigDef {name}_configs[] = {{")
+        for (bm, bn, t, bk) in cfgs:
+            reg.append(f"  {{{bm}, {bn}, {t}, {bk}}},")
+        reg.append("};")
+        reg.append(f"static const PartRef {name}_parts[] = {{")
+        for p in range(len(parts)):
+            reg.append(f"  {{{name}_part{p}, &{name}_part{p}_n}},")
+        if not parts:
+            reg.append("  {nullptr, nullptr},")
+        reg.append("};")
+        tables.append(f"  {{{name}_configs, {len(cfgs)}, {name}_parts, {len(parts)}}},")
+    reg.append("const DtypeRegistry dtype_registry[3] = {")
+    reg += tables
+    reg.append("};")
+    reg += ["}  // namespace kt", ""]
     path = os.path.join(out_dir, "registry_gen.cpp")
-    _write_if_changed(path, "\n".join(lines))
+    _write_if_changed(path, "\n".join(reg))
     paths.append(path)
     return paths
 
@@ -97,4 +140,5 @@ def _write_if_changed(path, text):
 if __name__ == "__main__":
     c = f32_configs()
     by_t = {t: sum(1 for x in c if x[2] == t) for t in THREAD_TILES}
-    print(len(c), by_t)
+    print("f32", len(c), by_t)
+    print("bf16/fp8", len(lp_configs()))

@@ -38,14 +38,17 @@ LaunchFn find_launcher(Ctx* h, int dtype, int32_t id, int ta, int tb) {
 }
 
 static void build_tables(Ctx* h) {
-  h->configs[KT_F32].assign(f32_config_table, f32_config_table + f32_config_count);
-  h->table[KT_F32].assign((size_t)f32_config_count * 4, nullptr);
-  for (int p = 0; p < f32_part_count; ++p) {
-    const PartRef& pr = f32_parts[p];
-    if (!pr.entries) continue;
-    for (int i = 0; i < *pr.count; ++i) {
-      const LaunchEntry& e = pr.entries[i];
-      h->table[KT_F32][(size_t)e.id * 4 + layout_index(e.ta, e.tb)] = e.fn;
+  for (int d = 0; d < NUM_DTYPES; ++d) {
+    const DtypeRegistry& r = dtype_registry[d];
+    h->configs[d].assign(r.configs, r.configs + r.n_configs);
+    h->table[d].assign((size_t)r.n_configs * 4, nullptr);
+    for (int p = 0; p < r.n_parts; ++p) {
+      const PartRef& pr = r.parts[p];
+      if (!pr.entries) continue;
+      for (int i = 0; i < *pr.count; ++i) {
+        const LaunchEntry& e = pr.entries[i];
+        h->table[d][(size_t)e.id * 4 + layout_index(e.ta, e.tb)] = e.fn;
+      }
     }
   }
 }
@@ -90,9 +93,10 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
   const int64_t tiles = cdiv(s->M, c.bm) * cdiv(s->N, c.bn);
   if (tiles > 0x7fffffffLL) return fail(h, KT_EINVAL, "problem too large for one grid");
   const int eb = elem_bytes(dtype);
-  const int vec_elems = 16 / eb;
+  // 16-byte vector loads need dword-aligned rows: pointer, leading dimension
+  // and batch stride all multiples of 4 bytes (FP32 always is).
   auto aligned = [&](const void* p, int64_t ld, int64_t st) {
-    return ((uintptr_t)p % 16 == 0) && (ld % vec_elems == 0) && (st % vec_elems == 0);
+    return ((uintptr_t)p % 4 == 0) && ((ld * eb) % 4 == 0) && ((st * eb) % 4 == 0);
   };
   GemmArgs g;
   memset(&g, 0, sizeof g);

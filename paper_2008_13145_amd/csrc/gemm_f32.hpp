@@ -31,11 +31,14 @@ struct GemmArgs {
   float* C; int64_t ldc, sC;
   float alpha, beta;
   const float* scaleA; const float* scaleB;   // FP8 only
-  int32_t vecA, vecB;   // 16-byte vector loads allowed (pointer, ld, stride aligned)
+  int32_t vecA, vecB;   // 16-byte aligned operands (pointer, ld, stride): low-precision paths
   int32_t tiles_m, tiles_n;
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Four floats with only 4-byte alignment: global_load_dwordx4 needs dword
+// alignment on CDNA, so rows of any leading dimension load as 16-byte vectors.
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Work-group id -> (tile_m, tile_n).  Consecutive work-group ids land on
@@ -70,9 +73,8 @@ struct TileLoader {
   f32x4 v[VPT];
 
   __device__ __forceinline__ void load(const float* __restrict__ base, int64_t ld, int64_t row0,
-                                       int64_t col0, int64_t row_lim, int64_t col_lim, bool vec,
-                                       int tid) {
-    const bool full = vec && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
+                                       int64_t col0, int64_t row_lim, int64_t col_lim, int tid) {
+    const bool full = (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int c = tid + i * NT;
@@ -81,12 +83,12 @@ struct TileLoader {
       const int64_t gr = row0 + r, gc = col0 + q;
       const float* p = base + gr * ld + gc;
       if (full) {
-        v[i] = *reinterpret_cast<const f32x4*>(p);
+        v[i] = *reinterpret_cast<const f32x4u*>(p);
       } else {
         f32x4 t = {0.f, 0.f, 0.f, 0.f};
         if (gr < row_lim) {
-          if (vec && gc + 4 <= col_lim) {
-            t = *reinterpret_cast<const f32x4*>(p);
+          if (gc + 4 <= col_lim) {
+            t = *reinterpret_cast<const f32x4u*>(p);
           } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -160,17 +162,16 @@ gemm_f32_kernel(GemmArgs args) {
   const int64_t M = args.M, N = args.N, K = args.K;
   const float* __restrict__ Ag = static_cast<const float*>(args.A) + bz * args.sA;
   const float* __restrict__ Bg = static_cast<const float*>(args.B) + bz * args.sB;
-  const bool vecA = args.vecA != 0, vecB = args.vecB != 0;
 
   // Loaders: the tile's contiguous dimension is the loader's COLS.
   TileLoader<(TA ? BK : BM), (TA ? BM : BK), NT> la;
   TileLoader<(TB ? BN : BK), (TB ? BK : BN), NT> lb;
 
   auto load_stage = [&](int64_t k0) {
-    if (TA) la.load(Ag, args.lda, k0, m0, K, M, vecA, tid);
-    else    la.load(Ag, args.lda, m0, k0, M, K, vecA, tid);
-    if (TB) lb.load(Bg, args.ldb, n0, k0, N, K, vecB, tid);
-    else    lb.load(Bg, args.ldb, k0, n0, K, N, vecB, tid);
+    if (TA) la.load(Ag, args.lda, k0, m0, K, M, tid);
+    else    la.load(Ag, args.lda, m0, k0, M, K, tid);
+    if (TB) lb.load(Bg, args.ldb, n0, k0, N, K, tid);
+    else    lb.load(Bg, args.ldb, k0, n0, K, N, tid);
   };
   auto store_stage = [&](int buf) {
     la.template store<TA == 0, Cfg::LDA_S>(As + buf * Cfg::A_STAGE, tid);

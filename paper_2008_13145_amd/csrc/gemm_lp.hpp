@@ -1,0 +1,256 @@
+// Low-precision GEMM family for gfx950: BF16 or FP8-e4m3 inputs, FP32
+// accumulation and output.  C_b = alpha * s * op(A_b) * op(B_b) + beta * C_b
+// with s = 1 for BF16 and s = 1 / (scaleA * scaleB) for per-tensor-scaled FP8.
+//
+// Same configuration knobs as the FP32 family (work-group tile BM x BN, per
+// wave an (8T) x (8T) block, K depth BK per LDS stage), with T in {4, 8}:
+// T = 4 is one 32x32 MFMA block per wave, T = 8 a 2x2 grid of them.
+// v_mfma_f32_32x32x16_bf16 / _fp8_fp8 take 8 consecutive K values per lane
+// (lane l: row l % 32, K offset 8 * (l / 32)), so both operands sit in LDS
+// with K contiguous ([m][k], [n][k]) and every fragment is one 16- (BF16) or
+// 8-byte (FP8) LDS read.  Rows are padded by 16 bytes so the 32 rows a
+// half-wave reads start on different banks.  An operand stored contiguous
+// along K is copied into LDS with 16-byte vectors; one stored contiguous
+// along M / N is transposed element by element on the way in.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gemm_f32.hpp"
+
+namespace kt {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int EB>   // element bytes: 2 = BF16, 1 = FP8 e4m3
+struct LpElem;
+template <>
+struct LpElem<2> { typedef uint16_t T; };
+template <>
+struct LpElem<1> { typedef uint8_t T; };
+
+// Global -> register staging of a ROWS x COLS tile (COLS contiguous in memory,
+// row stride ld elements), in 16-byte chunks.  Out-of-range elements read 0.
+template <int EB, int ROWS, int COLS, int NT>
+struct LpTileLoader {
+  typedef typename LpElem<EB>::T E;
+  static constexpr int EPC = 16 / EB;                 // elements per chunk
+  static constexpr int CV = COLS / EPC;               // chunks per row
+  static constexpr int NV = ROWS * CV;
+  static constexpr int VPT = (NV + NT - 1) / NT;
+  static_assert(COLS % EPC == 0, "tile row must hold whole 16-byte chunks");
+  u32x4 v[VPT];
+
+  __device__ __forceinline__ void load(const E* __restrict__ base, int64_t ld, int64_t row0,
+                                       int64_t col0, int64_t row_lim, int64_t col_lim, bool vec,
+                                       int tid) {
+    const bool full = vec && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int c = tid + i * NT;
+      if (NV % NT != 0 && c >= NV) { v[i] = u32x4{0u, 0u, 0u, 0u}; continue; }
+      const int r = c / CV, q = (c % CV) * EPC;
+      const int64_t gr = row0 + r, gc = col0 + q;
+      const E* p = base + gr * ld + gc;
+      if (full) {
+        v[i] = *reinterpret_cast<const u32x4u*>(p);
+      } else {
+        u32x4 t = {0u, 0u, 0u, 0u};
+        if (gr < row_lim) {
+          if (vec && gc + EPC <= col_lim) {
+            t = *reinterpret_cast<const u32x4u*>(p);
+          } else {
+            // element by element, packed little-endian into the chunk
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+              const uint32_t x = (gc + e < col_lim) ? (uint32_t)p[e] : 0u;
+              t[(e * EB) / 4] |= x << (8 * ((e * EB) % 4));
+            }
+          }
+        }
+        v[i] = t;
+      }
+    }
+  }
+
+  // DIRECT: element (r, c) -> lds[r * LD + c] (16-byte stores).
+  // TRANSPOSE: element (r, c) -> lds[c * LD + r] (element stores).
+  template <bool TRANSPOSE, int LD>
+  __device__ __forceinline__ void store(E* lds, int tid) const {
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int c = tid + i * NT;
+      if (NV % NT != 0 && c >= NV) continue;
+      const int r = c / CV, q = (c % CV) * EPC;
+      if (TRANSPOSE) {
+#pragma unroll
+        for (int e = 0; e < EPC; ++e)
+          lds[(q + e) * LD + r] = (E)(v[i][(e * EB) / 4] >> (8 * ((e * EB) % 4)));
+      } else {
+        *reinterpret_cast<u32x4*>(lds + r * LD + q) = v[i];
+      }
+    }
+  }
+};
+
+template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
+struct GemmLpCfg {
+  static constexpr int WT = 8 * T;
+  static constexpr int WAVES_N = BN / WT;
+  static constexpr int WAVES = (BM / WT) * WAVES_N;
+  static constexpr int NT = WAVES * 64;
+  static constexpr int PADK = 16 / EB;               // 16-byte row pad
+  static constexpr int LDK = BK + PADK;              // LDS row length (elements)
+  static constexpr int A_STAGE = BM * LDK;           // elements
+  static constexpr int B_STAGE = BN * LDK;
+  static constexpr int LDS_BYTES = 2 * (A_STAGE + B_STAGE) * EB;
+  static_assert(T == 4 || T == 8, "low-precision wave blocks are 32x32 or 64x64");
+  static_assert(BM % WT == 0 && BN % WT == 0, "tile must hold whole wave blocks");
+  static_assert(WAVES >= 1 && WAVES <= 16, "1..16 waves per work-group");
+  static_assert(BK % 16 == 0, "BK multiple of the MFMA K (16)");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+};
+
+template <int EB>
+__device__ __forceinline__ void lp_mfma(const void* a, const void* b, f32x16& c);
+
+template <>
+__device__ __forceinline__ void lp_mfma<2>(const void* a, const void* b, f32x16& c) {
+  const bf16x8 va = *reinterpret_cast<const bf16x8*>(a);
+  const bf16x8 vb = *reinterpret_cast<const bf16x8*>(b);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va, vb, c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ void lp_mfma<1>(const void* a, const void* b, f32x16& c) {
+  const long va = *reinterpret_cast<const long*>(a);
+  const long vb = *reinterpret_cast<const long*>(b);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(va, vb, c, 0, 0, 0);
+}
+
+// One BM x BN output tile (tile row tm, tile column tn) of batch item bz:
+// the whole K loop and the epilogue.  lds holds the two stages of both
+// operands; the caller synchronizes before reusing it for another tile.
+template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
+__device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, int64_t bz,
+                                        typename LpElem<EB>::T* lds) {
+  using Cfg = GemmLpCfg<EB, BM, BN, T, BK, TA, TB>;
+  typedef typename LpElem<EB>::T E;
+  constexpr int NT = Cfg::NT;
+  constexpr int WT = Cfg::WT;
+  constexpr int LDK = Cfg::LDK;
+  constexpr int SUB = T / 4;                 // 32x32 blocks per wave edge
+  E* As = lds;                               // [2][BM][LDK]
+  E* Bs = lds + 2 * Cfg::A_STAGE;            // [2][BN][LDK]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave / Cfg::WAVES_N) * WT;
+  const int wn0 = (wave % Cfg::WAVES_N) * WT;
+
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t M = args.M, N = args.N, K = args.K;
+  const E* __restrict__ Ag = static_cast<const E*>(args.A) + bz * args.sA;
+  const E* __restrict__ Bg = static_cast<const E*>(args.B) + bz * args.sB;
+  const bool vecA = args.vecA != 0, vecB = args.vecB != 0;
+
+  // A: TA == 0 -> k contiguous (direct), TA == 1 -> m contiguous (transpose).
+  LpTileLoader<EB, (TA ? BK : BM), (TA ? BM : BK), NT> la;
+  LpTileLoader<EB, (TB ? BN : BK), (TB ? BK : BN), NT> lb;
+
+  auto load_stage = [&](int64_t k0) {
+    if (TA) la.load(Ag, args.lda, k0, m0, K, M, vecA, tid);
+    else    la.load(Ag, args.lda, m0, k0, M, K, vecA, tid);
+    if (TB) lb.load(Bg, args.ldb, n0, k0, N, K, vecB, tid);
+    else    lb.load(Bg, args.ldb, k0, n0, K, N, vecB, tid);
+  };
+  auto store_stage = [&](int buf) {
+    la.template store<TA == 1, LDK>(As + buf * Cfg::A_STAGE, tid);
+    lb.template store<TB == 0, LDK>(Bs + buf * Cfg::B_STAGE, tid);
+  };
+
+  f32x16 acc[SUB][SUB];
+#pragma unroll
+  for (int i = 0; i < SUB; ++i)
+#pragma unroll
+    for (int j = 0; j < SUB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int r32 = lane & 31, kh = (lane >> 5) * 8;
+  const int nk = (int)((K + BK - 1) / BK);
+  if (nk > 0) {
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
+    const E* as = As + buf * Cfg::A_STAGE;
+    const E* bs = Bs + buf * Cfg::B_STAGE;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const E* ap[SUB];
+      const E* bp[SUB];
+#pragma unroll
+      for (int i = 0; i < SUB; ++i) {
+        ap[i] = as + (wm0 + 32 * i + r32) * LDK + kk + kh;
+        bp[i] = bs + (wn0 + 32 * i + r32) * LDK + kk + kh;
+      }
+#pragma unroll
+      for (int i = 0; i < SUB; ++i)
+#pragma unroll
+        for (int j = 0; j < SUB; ++j) lp_mfma<EB>(ap[i], bp[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) store_stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  float scale = args.alpha;
+  if (EB == 1) scale = args.alpha / (args.scaleA[0] * args.scaleB[0]);
+  float* __restrict__ Cg = args.C + bz * args.sC;
+  const float beta = args.beta;
+#pragma unroll
+  for (int i = 0; i < SUB; ++i)
+#pragma unroll
+    for (int j = 0; j < SUB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gi = m0 + wm0 + 32 * i + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int64_t gj = n0 + wn0 + 32 * j + r32;
+        if (gi < M && gj < N) {
+          float* p = Cg + gi * args.ldc + gj;
+          float out = scale * acc[i][j][r];
+          if (beta != 0.f) out = fmaf(beta, *p, out);
+          *p = out;
+        }
+      }
+}
+
+template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
+__global__ void __launch_bounds__(BM * BN / (T * T))
+gemm_lp_kernel(GemmArgs args) {
+  using Cfg = GemmLpCfg<EB, BM, BN, T, BK, TA, TB>;
+  typedef typename LpElem<EB>::T E;
+  __shared__ __attribute__((aligned(16))) E lds[Cfg::LDS_BYTES / EB];
+  int tm, tn;
+  tile_coords(blockIdx.x, args.tiles_m, args.tiles_n, tm, tn);
+  lp_tile<EB, BM, BN, T, BK, TA, TB>(args, tm, tn, (int64_t)blockIdx.y, lds);
+}
+
+template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
+hipError_t launch_gemm_lp(const GemmArgs& a, hipStream_t stream) {
+  using Cfg = GemmLpCfg<EB, BM, BN, T, BK, TA, TB>;
+  GemmArgs g = a;
+  g.tiles_m = (int)((a.M + BM - 1) / BM);
+  g.tiles_n = (int)((a.N + BN - 1) / BN);
+  dim3 grid((unsigned)((int64_t)g.tiles_m * g.tiles_n), (unsigned)a.batch, 1);
+  hipLaunchKernelGGL((gemm_lp_kernel<EB, BM, BN, T, BK, TA, TB>), grid, dim3(Cfg::NT), 0, stream, g);
+  return hipGetLastError();
+}
+
+}  // namespace kt

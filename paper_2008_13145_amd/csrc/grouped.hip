@@ -1,0 +1,384 @@
+// Persistent grouped BF16 GEMM: many uneven GEMMs in one launch, captured in
+// a hipGraph, with a tile schedule chosen by the library's own autotuner.
+//
+// The host flattens every member GEMM into output tiles (gemm, tile row,
+// tile column) in a chosen order -- as given, or longest-processing-time
+// first (largest K, then largest tile area) -- and uploads the member
+// descriptors and the work list.  A grid of (#CUs x work-groups per CU)
+// persistent work-groups then walks the list: statically (work-group b takes
+// items b, b + grid, ...) or dynamically (an atomic counter hands out the
+// next item; a one-thread kernel resets it inside the same graph).  Each
+// item runs the BF16 tile of the single-GEMM family (A row-major M x K, B
+// row-major K x N, FP32 C).
+//
+// The autotuner searches (tile configuration, schedule, order, work-groups
+// per CU) by successive halving on the real workload: every candidate's
+// graph is timed, the faster half kept, the repetitions doubled, until one
+// remains.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "gemm_lp.hpp"
+#include "kt_internal.hpp"
+
+namespace kt {
+
+struct GroupDesc {
+  const void* A;
+  const void* B;
+  float* C;
+  int64_t M, N, K, lda, ldb, ldc;
+  int32_t vecA, vecB;
+};
+
+struct WorkItem {
+  int32_t g, tm, tn, pad;
+};
+
+template <int BM, int BN, int T, int BK>
+__global__ void __launch_bounds__(BM * BN / (T * T))
+grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restrict__ work,
+                    int32_t n_work, float alpha, float beta, int32_t dynamic,
+                    uint32_t* __restrict__ counter, uint32_t* __restrict__ visits) {
+  using Cfg = GemmLpCfg<2, BM, BN, T, BK, 0, 0>;
+  __shared__ __attribute__((aligned(16))) uint16_t lds[Cfg::LDS_BYTES / 2];
+  __shared__ int32_t s_w;
+  int32_t w = blockIdx.x;
+  for (;;) {
+    if (dynamic) {
+      if (threadIdx.x == 0) s_w = (int32_t)atomicAdd(counter, 1u);
+      __syncthreads();
+      w = s_w;
+    }
+    if (w >= n_work) break;
+    const WorkItem it = work[w];
+    const GroupDesc d = descs[it.g];
+    GemmArgs a;
+    a.M = d.M; a.N = d.N; a.K = d.K; a.batch = 1;
+    a.A = d.A; a.lda = d.lda; a.sA = 0;
+    a.B = d.B; a.ldb = d.ldb; a.sB = 0;
+    a.C = d.C; a.ldc = d.ldc; a.sC = 0;
+    a.alpha = alpha; a.beta = beta;
+    a.scaleA = nullptr; a.scaleB = nullptr;
+    a.vecA = d.vecA; a.vecB = d.vecB;
+    a.tiles_m = 0; a.tiles_n = 0;
+    lp_tile<2, BM, BN, T, BK, 0, 0>(a, it.tm, it.tn, 0, lds);
+    if (visits && threadIdx.x == 0) atomicAdd(&visits[w], 1u);
+    __syncthreads();   // LDS and s_w are reused by the next item
+    if (!dynamic) w += gridDim.x;
+  }
+}
+
+__global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
+
+typedef void (*GroupedKernel)(const GroupDesc*, const WorkItem*, int32_t, float, float, int32_t,
+                              uint32_t*, uint32_t*);
+
+struct GroupedVariant {
+  int bm, bn, t, bk;
+  GroupedKernel fn;
+};
+
+// Tile configurations the grouped kernel is compiled for (a subset of the
+// BF16 configuration space).
+static const GroupedVariant kGroupedVariants[] = {
+    {64, 64, 4, 64, grouped_bf16_kernel<64, 64, 4, 64>},
+    {128, 64, 4, 64, grouped_bf16_kernel<128, 64, 4, 64>},
+    {64, 128, 4, 64, grouped_bf16_kernel<64, 128, 4, 64>},
+    {128, 128, 4, 32, grouped_bf16_kernel<128, 128, 4, 32>},
+    {128, 128, 8, 32, grouped_bf16_kernel<128, 128, 8, 32>},
+    {128, 128, 8, 64, grouped_bf16_kernel<128, 128, 8, 64>},
+    {256, 128, 8, 32, grouped_bf16_kernel<256, 128, 8, 32>},
+    {128, 256, 8, 32, grouped_bf16_kernel<128, 256, 8, 32>},
+};
+static constexpr int kNumVariants = sizeof(kGroupedVariants) / sizeof(kGroupedVariants[0]);
+
+static const GroupedVariant* variant_for(Ctx* h, int32_t config_id) {
+  if (config_id < 0 || config_id >= (int32_t)h->configs[KT_BF16].size()) return nullptr;
+  const ConfigDef& c = h->configs[KT_BF16][config_id];
+  for (int i = 0; i < kNumVariants; ++i) {
+    const GroupedVariant& v = kGroupedVariants[i];
+    if (v.bm == c.bm && v.bn == c.bn && v.t == c.t && v.bk == c.bk) return &v;
+  }
+  return nullptr;
+}
+
+static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Smallest tile of any variant bounds the work list length.
+static int64_t max_work_items(const kt_shape* s, int32_t n) {
+  int64_t tot = 0;
+  for (int32_t i = 0; i < n; ++i) tot += cdiv(s[i].M, 64) * cdiv(s[i].N, 64);
+  return tot;
+}
+
+}  // namespace kt
+
+struct kt_grouped_plan_s {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int32_t n_work = 0;
+  kt_grouped_opts opts;
+};
+
+using namespace kt;
+
+namespace kt {
+
+static kt_status validate_group(Ctx* h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                                const void* const* A, const void* const* B, float* const* C) {
+  if (dtype != KT_BF16) return fail(h, KT_EUNSUPPORTED, "grouped GEMM supports BF16 inputs");
+  if (n < 0 || (n > 0 && (!shapes || !A || !B || !C))) return fail(h, KT_EINVAL, "bad group arrays");
+  for (int32_t i = 0; i < n; ++i) {
+    const kt_shape& s = shapes[i];
+    if (s.M < 0 || s.N < 0 || s.K < 0) return fail(h, KT_EINVAL, "negative size in group");
+    if (s.batch != 1 || s.transA != 0 || s.transB != 0)
+      return fail(h, KT_EUNSUPPORTED, "grouped members must be batch 1, transA = transB = 0");
+    if (s.M > 0 && s.N > 0 && (!C[i] || (s.K > 0 && (!A[i] || !B[i]))))
+      return fail(h, KT_EINVAL, "NULL member pointer");
+  }
+  return KT_OK;
+}
+
+static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const void* const* A,
+                            const void* const* B, float* const* C, float alpha, float beta,
+                            const kt_grouped_opts& o, void* ws, size_t ws_bytes, hipStream_t stream,
+                            kt_grouped_plan_s** out) {
+  const GroupedVariant* v = variant_for(h, o.config_id);
+  if (!v) return fail(h, KT_EUNSUPPORTED, "BF16 configuration not compiled for the grouped kernel");
+  if (o.schedule < 0 || o.schedule > 1 || o.order < 0 || o.order > 1 || o.wgs_per_cu < 1 || o.wgs_per_cu > 4)
+    return fail(h, KT_EINVAL, "bad grouped options");
+  const size_t need = a256((size_t)n * sizeof(GroupDesc)) + a256((size_t)max_work_items(shapes, n) * sizeof(WorkItem)) + 256;
+  if (!ws || ws_bytes < need) return fail(h, KT_EWORKSPACE, "grouped workspace too small");
+  std::vector<GroupDesc> descs(n);
+  for (int32_t i = 0; i < n; ++i) {
+    const kt_shape& s = shapes[i];
+    GroupDesc& d = descs[i];
+    d.A = A[i]; d.B = B[i]; d.C = C[i];
+    d.M = s.M; d.N = s.N; d.K = s.K;
+    d.lda = std::max<int64_t>(s.K, 1); d.ldb = std::max<int64_t>(s.N, 1); d.ldc = std::max<int64_t>(s.N, 1);
+    d.vecA = ((uintptr_t)A[i] % 4 == 0) && (d.lda % 2 == 0);
+    d.vecB = ((uintptr_t)B[i] % 4 == 0) && (d.ldb % 2 == 0);
+  }
+  std::vector<int32_t> gorder(n);
+  std::iota(gorder.begin(), gorder.end(), 0);
+  if (o.order == 1)   // longest processing time first: tile work grows with K
+    std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return shapes[a].K > shapes[b].K; });
+  std::vector<WorkItem> work;
+  for (int32_t g : gorder) {
+    const kt_shape& s = shapes[g];
+    if (s.M == 0 || s.N == 0) continue;
+    const int tmn = (int)cdiv(s.M, v->bm), tnn = (int)cdiv(s.N, v->bn);
+    for (int tm = 0; tm < tmn; ++tm)
+      for (int tn = 0; tn < tnn; ++tn) work.push_back(WorkItem{g, tm, tn, 0});
+  }
+  char* w = (char*)ws;
+  GroupDesc* d_desc = (GroupDesc*)w;
+  WorkItem* d_work = (WorkItem*)(w + a256((size_t)n * sizeof(GroupDesc)));
+  uint32_t* d_counter = (uint32_t*)(w + a256((size_t)n * sizeof(GroupDesc)) +
+                                    a256((size_t)max_work_items(shapes, n) * sizeof(WorkItem)));
+  hipError_t e = hipSuccess;
+  if (n > 0) e = hipMemcpyAsync(d_desc, descs.data(), n * sizeof(GroupDesc), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && !work.empty())
+    e = hipMemcpyAsync(d_work, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(h, e, "upload grouped work list");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, h->device)) != hipSuccess) return hip_fail(h, e, "device properties");
+  const int n_work = (int)work.size();
+  const int grid = std::max(1, std::min(n_work, prop.multiProcessorCount * o.wgs_per_cu));
+  const int threads = v->bm * v->bn / (v->t * v->t);
+  hipStream_t cs;
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(h, e, "capture stream");
+  kt_grouped_plan_s* plan = new kt_grouped_plan_s();
+  plan->n_work = n_work;
+  plan->opts = o;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess && n_work > 0) {
+    if (o.schedule == 1) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, cs, d_counter);
+    hipLaunchKernelGGL(v->fn, dim3(grid), dim3(threads), 0, cs, (const GroupDesc*)d_desc,
+                       (const WorkItem*)d_work, n_work, alpha, beta, (int32_t)o.schedule, d_counter,
+                       o.visits);
+  }
+  hipError_t e2 = hipStreamEndCapture(cs, &plan->graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return hip_fail(h, e, "grouped graph capture");
+  }
+  *out = plan;
+  return KT_OK;
+}
+
+static void plan_free(kt_grouped_plan_s* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  delete p;
+}
+
+static kt_grouped_opts default_grouped_opts(Ctx* h) {
+  kt_grouped_opts o;
+  memset(&o, 0, sizeof o);
+  o.config_id = -1;
+  for (int32_t i = 0; i < (int32_t)h->configs[KT_BF16].size(); ++i) {
+    const ConfigDef& c = h->configs[KT_BF16][i];
+    if (c.bm == 128 && c.bn == 128 && c.t == 8 && c.bk == 32) o.config_id = i;
+  }
+  o.schedule = 1;
+  o.order = 1;
+  o.wgs_per_cu = 2;
+  return o;
+}
+
+}  // namespace kt
+
+extern "C" {
+
+kt_status kt_grouped_workspace_bytes(const kt_shape* shapes, int32_t n, size_t* bytes) {
+  if (!bytes || n < 0 || (n > 0 && !shapes)) return KT_EINVAL;
+  *bytes = a256((size_t)n * sizeof(GroupDesc)) + a256((size_t)max_work_items(shapes, n) * sizeof(WorkItem)) + 256;
+  return KT_OK;
+}
+
+kt_status kt_grouped_num_candidates(int32_t* n) {
+  if (!n) return KT_EINVAL;
+  *n = kNumVariants;
+  return KT_OK;
+}
+
+kt_status kt_grouped_plan_create(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                                 const void* const* A, const void* const* B, float* const* C,
+                                 float alpha, float beta, const kt_grouped_opts* opts,
+                                 void* workspace, size_t ws_bytes, void* stream,
+                                 kt_grouped_plan* out) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!need_device(h)) return KT_EINVAL;
+  if (!out) return fail(h, KT_EINVAL, "NULL plan output");
+  kt_status s = validate_group(h, dtype, shapes, n, A, B, C);
+  if (s != KT_OK) return s;
+  kt_grouped_opts o = opts ? *opts : (h->grouped_tuned ? h->grouped_best : default_grouped_opts(h));
+  kt_grouped_plan_s* p = nullptr;
+  s = plan_build(h, shapes, n, A, B, C, alpha, beta, o, workspace, ws_bytes, (hipStream_t)stream, &p);
+  if (s != KT_OK) return s;
+  *out = p;
+  return KT_OK;
+}
+
+kt_status kt_grouped_plan_launch(kt_handle hh, kt_grouped_plan plan, void* stream) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!plan) return fail(h, KT_EINVAL, "NULL plan");
+  if (plan->n_work == 0) return KT_OK;
+  hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(h, e, "grouped graph launch");
+  return KT_OK;
+}
+
+kt_status kt_grouped_plan_info(kt_grouped_plan plan, int32_t* n_work, kt_grouped_opts* opts) {
+  if (!plan) return KT_EINVAL;
+  if (n_work) *n_work = plan->n_work;
+  if (opts) *opts = plan->opts;
+  return KT_OK;
+}
+
+kt_status kt_grouped_plan_destroy(kt_grouped_plan plan) {
+  plan_free(plan);
+  return KT_OK;
+}
+
+kt_status kt_grouped_gemm(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                          const void* const* A, const void* const* B, float* const* C, float alpha,
+                          float beta, const kt_grouped_opts* opts, void* workspace, size_t ws_bytes,
+                          void* stream) {
+  kt_grouped_plan p = nullptr;
+  kt_status s = kt_grouped_plan_create(hh, dtype, shapes, n, A, B, C, alpha, beta, opts, workspace,
+                                       ws_bytes, stream, &p);
+  if (s != KT_OK) return s;
+  s = kt_grouped_plan_launch(hh, p, stream);
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  plan_free(p);
+  if (s == KT_OK && e != hipSuccess) s = hip_fail(h, e, "grouped sync");
+  return s;
+}
+
+kt_status kt_autotune_grouped(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t n,
+                              const void* const* A, const void* const* B, float* const* C,
+                              void* workspace, size_t ws_bytes, void* stream,
+                              kt_grouped_opts* best, float* best_ms, int32_t* evaluations) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!need_device(h)) return KT_EINVAL;
+  kt_status s = validate_group(h, dtype, shapes, n, A, B, C);
+  if (s != KT_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<kt_grouped_opts> cands;
+  for (int vi = 0; vi < kNumVariants; ++vi) {
+    int32_t id = -1;
+    for (int32_t i = 0; i < (int32_t)h->configs[KT_BF16].size(); ++i) {
+      const ConfigDef& c = h->configs[KT_BF16][i];
+      const GroupedVariant& v = kGroupedVariants[vi];
+      if (c.bm == v.bm && c.bn == v.bn && c.t == v.t && c.bk == v.bk) id = i;
+    }
+    if (id < 0) continue;
+    for (int sched = 0; sched < 2; ++sched)
+      for (int order = 0; order < 2; ++order)
+        for (int wgs = 1; wgs <= 2; ++wgs) {
+          kt_grouped_opts o;
+          memset(&o, 0, sizeof o);
+          o.config_id = id; o.schedule = sched; o.order = order; o.wgs_per_cu = wgs;
+          cands.push_back(o);
+        }
+  }
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return hip_fail(h, e, "event");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(h, e, "event"); }
+  std::vector<float> score(cands.size(), 0.f);
+  std::vector<int> alive(cands.size());
+  std::iota(alive.begin(), alive.end(), 0);
+  int reps = 1, evals = 0;
+  while (s == KT_OK) {
+    for (int ci : alive) {
+      kt_grouped_plan_s* p = nullptr;
+      s = plan_build(h, shapes, n, A, B, C, 1.f, 0.f, cands[ci], workspace, ws_bytes, st, &p);
+      if (s != KT_OK) break;
+      e = hipGraphLaunch(p->exec, st);                   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(p->exec, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      plan_free(p);
+      if (e != hipSuccess) { s = hip_fail(h, e, "autotune timing"); break; }
+      score[ci] = ms / reps;
+      ++evals;
+    }
+    if (s != KT_OK || alive.size() == 1) break;
+    std::stable_sort(alive.begin(), alive.end(), [&](int a, int b) { return score[a] < score[b]; });
+    alive.resize((alive.size() + 1) / 2);
+    reps *= 2;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != KT_OK) return s;
+  h->grouped_best = cands[alive[0]];
+  h->grouped_tuned = true;
+  if (best) *best = cands[alive[0]];
+  if (best_ms) *best_ms = score[alive[0]];
+  if (evaluations) *evaluations = evals;
+  return KT_OK;
+}
+
+}  // extern "C"

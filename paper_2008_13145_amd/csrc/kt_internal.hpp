@@ -54,6 +54,8 @@ struct Ctx {
   size_t scratch_bytes = 0;
   std::vector<uint16_t> sigmoid_lut;
   void* d_lut = nullptr;           // device sigmoid table (handle-owned)
+  kt_grouped_opts grouped_best{};  // autotuner result for grouped GEMM
+  bool grouped_tuned = false;
 };
 
 // Record an error message on the handle and return the status.

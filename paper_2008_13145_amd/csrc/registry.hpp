@@ -25,9 +25,14 @@ struct PartRef {
   const int* count;
 };
 
-extern const ConfigDef f32_config_table[];
-extern const int f32_config_count;
-extern const PartRef f32_parts[];
-extern const int f32_part_count;
+struct DtypeRegistry {
+  const ConfigDef* configs;   // the configuration space of the dtype (id = index)
+  int n_configs;
+  const PartRef* parts;       // compiled instantiations
+  int n_parts;
+};
+
+// Indexed by kt_dtype (F32, BF16, FP8E4M3).
+extern const DtypeRegistry dtype_registry[3];
 
 }  // namespace kt

@@ -24,7 +24,9 @@ struct OperandPlan {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Dense operands of one problem, packed in a workspace.
+// Dense operands of one problem, packed in a workspace: A, B (element type of
+// the dtype), C (FP32), then for BF16 / FP8 an FP32 staging area the operands
+// are generated in before conversion, and two FP8 scales plus the amax slot.
 static OperandPlan plan_for(const kt_shape& s, int dtype) {
   OperandPlan p;
   const int64_t eb = elem_bytes_of(dtype);
@@ -36,13 +38,43 @@ static OperandPlan plan_for(const kt_shape& s, int dtype) {
   p.sA = a_rows * p.lda;
   p.sB = b_rows * p.ldb;
   p.sC = s.M * p.ldc;
-  // FP32 staging for low-precision operands is placed after C.
   p.offA = 0;
   p.offB = align256(p.offA + (size_t)(s.batch * p.sA * eb));
   p.offC = align256(p.offB + (size_t)(s.batch * p.sB * eb));
   p.offS = align256(p.offC + (size_t)(s.batch * p.sC * 4));
-  p.total = align256(p.offS + 256);
+  size_t stage = 0;
+  if (dtype != KT_F32) stage = (size_t)std::max(s.batch * p.sA, s.batch * p.sB) * 4;
+  p.total = align256(p.offS + 256 + stage);
   return p;
+}
+
+// Fill the operands of one problem (row r of a sweep) on the device.
+static hipError_t fill_operands(int dtype, const OperandPlan& p, const kt_shape& s, char* ws,
+                                uint64_t base, hipStream_t stream, Ctx* h) {
+  float* C = (float*)(ws + p.offC);
+  hipError_t e = fill_uniform(C, s.batch * p.sC, base + 2, 0, stream);
+  if (e != hipSuccess) return e;
+  if (dtype == KT_F32) {
+    e = fill_uniform((float*)(ws + p.offA), s.batch * p.sA, base + 0, 0, stream);
+    if (e == hipSuccess) e = fill_uniform((float*)(ws + p.offB), s.batch * p.sB, base + 1, 0, stream);
+    return e;
+  }
+  float* stage = (float*)(ws + p.offS + 256);
+  float* scales = (float*)(ws + p.offS);
+  for (int which = 0; which < 2; ++which) {
+    const int64_t n = s.batch * (which == 0 ? p.sA : p.sB);
+    void* dst = ws + (which == 0 ? p.offA : p.offB);
+    e = fill_uniform(stage, n, base + which, 0, stream);
+    if (e != hipSuccess) return e;
+    kt_status st;
+    if (dtype == KT_BF16)
+      st = kt_convert_bf16(reinterpret_cast<kt_handle>(h), stage, n, (uint16_t*)dst, stream);
+    else
+      st = kt_quantize_fp8(reinterpret_cast<kt_handle>(h), stage, n, (uint8_t*)dst, scales + which,
+                           scales + 2, 16, stream);
+    if (st != KT_OK) return hipErrorLaunchFailure;
+  }
+  return hipSuccess;
 }
 
 }  // namespace kt
@@ -54,7 +86,7 @@ extern "C" {
 kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_dtype dtype,
                                    size_t* bytes) {
   if (!bytes || (n_shapes > 0 && !shapes) || n_shapes < 0) return KT_EINVAL;
-  if ((int)dtype != KT_F32) return KT_EUNSUPPORTED;
+  if ((int)dtype < 0 || (int)dtype > KT_FP8E4M3) return KT_EINVAL;
   size_t m = 0;
   for (int32_t i = 0; i < n_shapes; ++i) {
     if (shapes[i].M < 0 || shapes[i].N < 0 || shapes[i].K < 0 || shapes[i].batch < 0) return KT_EINVAL;
@@ -70,7 +102,7 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!need_device(h)) return KT_EINVAL;
-  if ((int)dtype != KT_F32) return fail(h, KT_EUNSUPPORTED, "sweep supports FP32 operands");
+  if ((int)dtype < 0 || (int)dtype > KT_FP8E4M3) return fail(h, KT_EINVAL, "bad dtype");
   if (n_shapes < 0 || (n_shapes > 0 && (!shapes || !time_ns)) || !opts)
     return fail(h, KT_EINVAL, "bad shapes / time_ns / opts");
   std::vector<int32_t> ids;
@@ -112,14 +144,13 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
     OperandPlan p = plan_for(s, dtype);
     if (!workspace || ws_bytes < p.total) { result = fail(h, KT_EWORKSPACE, "sweep workspace too small"); break; }
     char* ws = (char*)workspace;
-    float* A = (float*)(ws + p.offA);
-    float* B = (float*)(ws + p.offB);
+    const void* A = ws + p.offA;
+    const void* B = ws + p.offB;
     float* C = (float*)(ws + p.offC);
+    const float* scales = (const float*)(ws + p.offS);
     const uint64_t base = opts->seed * 0x100000001B3ull + (uint64_t)r * 4;
-    he = fill_uniform(A, s.batch * p.sA, base + 0, 0, stream);
-    if (he == hipSuccess) he = fill_uniform(B, s.batch * p.sB, base + 1, 0, stream);
-    if (he == hipSuccess) he = fill_uniform(C, s.batch * p.sC, base + 2, 0, stream);
-    if (he != hipSuccess) { result = hip_fail(h, he, "operand fill"); break; }
+    he = fill_operands(dtype, p, s, ws, base, stream, h);
+    if (he != hipSuccess) { result = fail(h, KT_EHIP, "operand fill / conversion failed"); break; }
     double best_ms = -1.0;
     for (int32_t c = 0; c < n_configs; ++c) if (row[c] > 0) {
       const double ms = row[c] * 1e-6;
@@ -131,7 +162,7 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
       const int32_t id = ids[c];
       auto launch = [&]() {
         return launch_gemm(h, dtype, &s, opts->alpha, A, p.lda, p.sA, B, p.ldb, p.sB,
-                           opts->beta, C, p.ldc, p.sC, nullptr, nullptr, id, stream);
+                           opts->beta, C, p.ldc, p.sC, scales, scales + 1, id, stream);
       };
       for (int w = 0; w < opts->warmup && result == KT_OK; ++w) result = launch();
       if (result != KT_OK) break;

@@ -1,0 +1,145 @@
+"""Offline tuning driver: the benchmark sweep that builds the dataset the
+pruning and selection learn from (sections 3 and 3.1 of the paper), and the
+deploy build that keeps only the pruned kernels (section 4).
+
+    python -m paper_2008_13145_amd.tune sweep --out TABLE.npz [--budget-s 900]
+    python -m paper_2008_13145_amd.tune deploy --table TABLE.npz --k 8
+
+The sweep is resumable: the table is saved after every chunk of rows, and a
+restart skips rows already measured (entries >= 0).  Problems are the 300
+seeded log-uniform shapes of ``synth.sweep_shapes()`` in all four layouts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "data", "sweep_f32_mi355x.npz")
+DEPLOY_SPEC = os.path.join(HERE, "data", "deploy_f32.json")
+DEPLOY_LIB = os.path.join(HERE, "libkt_deploy.so")
+
+
+def load_table(path):
+    """(time_ns int64 [P][C], problems int64 [P][6], configs int32 [C][4], meta dict)."""
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+        return z["time_ns"].copy(), z["problems"].copy(), z["configs"].copy(), meta
+
+
+def save_table(path, time_ns, problems, configs, meta):
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp.npz"
+    np.savez_compressed(tmp, time_ns=time_ns, problems=np.asarray(problems, np.int64),
+                        configs=np.asarray(configs, np.int32), meta=np.array(json.dumps(meta)))
+    os.replace(tmp, path)
+
+
+def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
+              cut_factor=8.0, warmup=0, limit=None, log=print):
+    import torch
+
+    import synth
+    from . import Handle
+    h = Handle(0)
+    problems = synth.sweep_problems()
+    if limit:
+        problems = problems[:limit]
+    configs = h.configs()
+    if os.path.exists(out):
+        T, P, C, meta = load_table(out)
+        if P.tolist() != [list(p) for p in problems] or C.tolist() != [list(c) for c in configs]:
+            raise RuntimeError(f"{out} was made for another problem set or configuration space")
+    else:
+        T = np.full((len(problems), len(configs)), -1, np.int64)
+        props = torch.cuda.get_device_properties(0)
+        meta = dict(device=props.name, arch=getattr(props, "gcnArchName", ""),
+                    opts=dict(target_ms=target_ms, min_reps=min_reps, max_reps=max_reps,
+                              cut_factor=cut_factor, warmup=warmup),
+                    seed=synth.SEED, started=time.time(), seconds=0.0)
+    ws_bytes = Handle.sweep_workspace_bytes(problems)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    # Load every kernel once on a tiny problem, so that no row pays for code
+    # object loading and the first timed launch of a pair is representative.
+    tiny = [(8, 8, 8, 1, ta, tb) for (ta, tb) in synth.LAYOUTS]
+    h.sweep(tiny, ws, ws_bytes, warmup=0, target_ms=0.0, min_reps=1, max_reps=1, cut_factor=0.0)
+    t0 = time.time()
+    last_save = time.time()
+    todo = [i for i in range(len(problems)) if (T[i] < 0).any()]
+    log(f"sweep: {len(todo)} of {len(problems)} rows left, workspace {ws_bytes / 2**30:.2f} GiB", flush=True)
+    for n_done, i in enumerate(todo):
+        if time.time() - t0 > budget_s:
+            log("sweep: time budget reached; rerun to resume", flush=True)
+            break
+        sub = T[i:i + 1].copy()
+        ts = time.time()
+        h.sweep([problems[i]], ws, ws_bytes, time_ns=sub, warmup=warmup, target_ms=target_ms,
+                min_reps=min_reps, max_reps=max_reps, cut_factor=cut_factor)
+        T[i] = sub[0]
+        meta["seconds"] = meta.get("seconds", 0.0) + (time.time() - ts)
+        if time.time() - last_save > 20 or n_done == len(todo) - 1:
+            meta["finished"] = bool((T >= 0).all())
+            save_table(out, T, problems, configs, meta)
+            last_save = time.time()
+        M, N, K, b, ta, tb = problems[i]
+        best = int(T[i].min())
+        log(f"sweep: row {i} ({M}x{N}x{K}x{b} {ta}{tb}) best {configs[int(T[i].argmin())]} "
+            f"{2 * M * N * K * b / best / 1e3:.1f} TF, {time.time() - ts:.1f}s; "
+            f"{int((T >= 0).all(axis=1).sum())}/{len(problems)} done", flush=True)
+    meta["finished"] = bool((T >= 0).all())
+    save_table(out, T, problems, configs, meta)
+    return T
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("sweep")
+    s.add_argument("--out", default=DEFAULT_TABLE)
+    s.add_argument("--budget-s", type=float, default=900.0)
+    s.add_argument("--limit", type=int, default=None)
+    d = sub.add_parser("deploy")
+    d.add_argument("--table", default=DEFAULT_TABLE)
+    d.add_argument("--k", type=int, default=8)
+    d.add_argument("--spec", default=DEPLOY_SPEC)
+    d.add_argument("--out", default=DEPLOY_LIB)
+    d.add_argument("--no-build", action="store_true")
+    a = ap.parse_args(argv)
+    if a.cmd == "sweep":
+        run_sweep(a.out, a.budget_s, limit=a.limit)
+    elif a.cmd == "deploy":
+        # choose the k kernels by GPU k-means over the training problems of the
+        # measured table, record them, and build the library with only those
+        import torch
+
+        import synth
+        from . import NORM_RELATIVE, Handle, build
+        T, P, C, meta = load_table(a.table)
+        train, _ = synth.train_test_split()
+        rows = synth.rows_of_shapes(train)
+        h = Handle(0)
+        ws_bytes = Handle.prune_workspace_bytes(len(rows), T.shape[1], a.k, 10)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        res = h.prune(T[rows], a.k, norm=NORM_RELATIVE, seed=synth.SEED, n_init=10, max_iter=300,
+                      workspace=ws, ws_bytes=ws_bytes)
+        chosen = res["chosen"]
+        spec = dict(dtype="f32", k=a.k, chosen=chosen, configs=[list(map(int, C[i])) for i in chosen],
+                    norm="relative", seed=synth.SEED, n_init=10, max_iter=300,
+                    table=os.path.relpath(a.table, HERE), device=meta.get("device"),
+                    inertia=int(res["inertia"]))
+        os.makedirs(os.path.dirname(a.spec), exist_ok=True)
+        with open(a.spec, "w") as f:
+            json.dump(spec, f, indent=1)
+        print("chosen", chosen, spec["configs"], flush=True)
+        if not a.no_build:
+            build.build(f32_ids=chosen, lp_ids=[], out=a.out, tag="deploy", verbose=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,229 @@
+"""GPU parity of the BF16 and FP8-e4m3 paths against the CPU oracle.
+
+Accuracy bar: relative Frobenius error per result (per batch item) against
+the FP64 oracle on the original FP32 operands <= 1e-2 (BF16) and <= 4e-2
+(FP8).  The kernel itself is checked tighter against the oracle on the
+dequantized operands (FP32-accumulation bound), and bit for bit where every
+value and partial sum is exact."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import convert as cv
+from oracle import gemm as og
+
+pytestmark = pytest.mark.gpu
+
+BF16, FP8 = 1, 2
+
+
+def _values(n, seed):
+    x = synth.uniform_operand(seed, n).astype(np.float32)
+    e = (synth.uniform_operand(seed + 1, n) * 24).astype(np.int32).astype(np.float32)
+    return (x * np.float32(2.0) ** e).astype(np.float32)
+
+
+def test_bf16_conversion_bitwise(gpu):
+    h, torch = gpu
+    x = np.concatenate([_values(1_000_003, 5),
+                        np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 3.4e38, -3.4e38, 1e-40,
+                                  1.00390625, 1.01171875], np.float32)])
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.zeros(x.size, dtype=torch.int16, device="cuda")
+    h.convert_bf16(dx, x.size, dy)
+    torch.cuda.synchronize()
+    assert np.array_equal(dy.cpu().numpy().view(np.uint16), cv.bf16_rne(x))
+
+
+@pytest.mark.parametrize("scale_exp", [0, -20, 12])
+def test_fp8_quantization_bitwise(gpu, scale_exp):
+    h, torch = gpu
+    x = (synth.uniform_operand(7 + scale_exp, 1_000_001) * np.float32(2.0 ** scale_exp)).astype(np.float32)
+    x[::1000] = 0.0
+    x[5] = -x[5]
+    dx = torch.from_numpy(x).cuda()
+    dy = torch.zeros(x.size, dtype=torch.uint8, device="cuda")
+    ds = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = torch.zeros(4, dtype=torch.int32, device="cuda")
+    h.quantize_fp8(dx, x.size, dy, ds, ws, 16)
+    torch.cuda.synchronize()
+    codes, s = cv.quantize_fp8(x)
+    assert ds.item() == float(s)
+    assert np.array_equal(dy.cpu().numpy(), codes)
+
+
+def test_fp8_quantization_zero_and_empty(gpu):
+    h, torch = gpu
+    dx = torch.zeros(100, dtype=torch.float32, device="cuda")
+    dy = torch.full((100,), 7, dtype=torch.uint8, device="cuda")
+    ds = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = torch.zeros(4, dtype=torch.int32, device="cuda")
+    h.quantize_fp8(dx, 100, dy, ds, ws, 16)
+    torch.cuda.synchronize()
+    assert ds.item() == 1.0 and not dy.cpu().numpy().any()
+    h.quantize_fp8(dx, 0, dy, ds, ws, 16)
+    torch.cuda.synchronize()
+    assert ds.item() == 1.0
+
+
+def _stored(a_op, trans):
+    return np.ascontiguousarray(np.transpose(a_op, (0, 2, 1)) if trans else a_op)
+
+
+def _prepare(h, torch, a, b, ta, tb, dtype):
+    """Device operands of dtype from FP32 op() matrices; returns tensors, the
+    dequantized op() matrices (float64) and the scale tensors."""
+    As, Bs = _stored(a, ta), _stored(b, tb)
+    dA32 = torch.from_numpy(As).cuda()
+    dB32 = torch.from_numpy(Bs).cuda()
+    if dtype == BF16:
+        dA = torch.zeros(As.shape, dtype=torch.int16, device="cuda")
+        dB = torch.zeros(Bs.shape, dtype=torch.int16, device="cuda")
+        h.convert_bf16(dA32, As.size, dA)
+        h.convert_bf16(dB32, Bs.size, dB)
+        deq_a = cv.bf16_decode(cv.bf16_rne(a)).astype(np.float64)
+        deq_b = cv.bf16_decode(cv.bf16_rne(b)).astype(np.float64)
+        return dA, dB, None, None, deq_a, deq_b
+    dA = torch.zeros(As.shape, dtype=torch.uint8, device="cuda")
+    dB = torch.zeros(Bs.shape, dtype=torch.uint8, device="cuda")
+    sA = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sB = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = torch.zeros(4, dtype=torch.int32, device="cuda")
+    h.quantize_fp8(dA32, As.size, dA, sA, ws, 16)
+    h.quantize_fp8(dB32, Bs.size, dB, sB, ws, 16)
+    qa, sa = cv.quantize_fp8(a)
+    qb, sb = cv.quantize_fp8(b)
+    deq_a = cv.e4m3_decode(qa) / np.float64(sa)
+    deq_b = cv.e4m3_decode(qb) / np.float64(sb)
+    return dA, dB, sA, sB, deq_a, deq_b
+
+
+def _gemm(h, torch, dtype, dA, dB, sA, sB, shape, ta, tb, alpha, beta, c0, cfg):
+    import paper_2008_13145_amd as kt
+    bt, M, N = c0.shape
+    K = shape
+    dC = torch.from_numpy(c0.copy()).cuda()
+    lda = M if ta else K
+    ldb = K if tb else N
+    h.gemm_raw(dtype, kt.shape(M, N, K, bt, ta, tb), alpha, dA, lda, M * K, dB, ldb, K * N, beta,
+               dC, N, M * N, scaleA=sA, scaleB=sB, config_id=cfg)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+def _ref(a, b, c0, alpha, beta):
+    bt, M, K = a.shape
+    N = b.shape[2]
+    return og.gemm(M, N, K, bt, 0, 0, alpha, beta, a.astype(np.float32), K, M * K,
+                   b.astype(np.float32), N, K * N, c0, N, M * N)
+
+
+def _ref64(a, b, c0, alpha, beta):
+    # exact-input reference for dequantized operands (not representable in FP32 for FP8)
+    out = alpha * np.einsum("bik,bkj->bij", a, b)
+    if beta != 0:
+        out = out + beta * c0.astype(np.float64)
+    return out
+
+
+@pytest.mark.parametrize("dtype", [BF16, FP8])
+@pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
+def test_all_configs_accuracy(gpu, dtype, ta, tb):
+    h, torch = gpu
+    M, N, K, bt = 300, 270, 200, 2
+    a = synth.uniform_operand(synth.operand_seed(50 + ta, 0), bt * M * K).reshape(bt, M, K)
+    b = synth.uniform_operand(synth.operand_seed(50 + tb, 1), bt * K * N).reshape(bt, K, N)
+    c0 = synth.uniform_operand(synth.operand_seed(52, 2), bt * M * N).reshape(bt, M, N)
+    dA, dB, sA, sB, deq_a, deq_b = _prepare(h, torch, a, b, ta, tb, dtype)
+    alpha, beta = 1.0, 0.0
+    ref = _ref(a, b, c0, alpha, beta)
+    ref_q = _ref64(deq_a, deq_b, c0, alpha, beta)
+    bound = 1e-2 if dtype == BF16 else 4e-2
+    tol_q = 1e-5 * math.sqrt(K) * np.abs(deq_a).max() * np.abs(deq_b).max()
+    bad = []
+    worst = 0.0
+    for cfg in range(h.num_configs(dtype)):
+        got = _gemm(h, torch, dtype, dA, dB, sA, sB, K, ta, tb, alpha, beta,
+                    np.full_like(c0, np.nan), cfg)
+        for i in range(bt):
+            e = cv.rel_frobenius(got[i], ref[i])
+            worst = max(worst, e)
+            if not e <= bound or not np.all(np.abs(got[i] - ref_q[i]) <= tol_q):
+                bad.append((cfg, h.get_config(cfg, dtype), e))
+    assert not bad, bad[:8]
+
+
+@pytest.mark.parametrize("dtype", [BF16, FP8])
+@pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
+def test_all_configs_exact_integers(gpu, dtype, ta, tb):
+    """Integers in [-7, 7]: exact in BF16, and exact in FP8 after the scale
+    448 / 7 = 64 (a power of two); all partial sums exact in FP32, so every
+    configuration equals the oracle bit for bit."""
+    h, torch = gpu
+    M, N, K, bt = 133, 96, 160, 2
+    rng = np.random.default_rng(ta * 2 + tb)
+    a = rng.integers(-7, 8, size=(bt, M, K)).astype(np.float32)
+    b = rng.integers(-7, 8, size=(bt, K, N)).astype(np.float32)
+    a[:, 0, 0] = 7
+    b[:, 0, 0] = -7
+    c0 = np.zeros((bt, M, N), np.float32)
+    dA, dB, sA, sB, _, _ = _prepare(h, torch, a, b, ta, tb, dtype)
+    ref = _ref(a, b, c0, 1.0, 0.0)
+    bad = []
+    for cfg in range(h.num_configs(dtype)):
+        got = _gemm(h, torch, dtype, dA, dB, sA, sB, K, ta, tb, 1.0, 0.0, np.full_like(c0, np.nan), cfg)
+        if not np.array_equal(got.astype(np.float64), ref):
+            bad.append((cfg, h.get_config(cfg, dtype)))
+    assert not bad, bad[:8]
+
+
+@pytest.mark.parametrize("dtype", [BF16, FP8])
+def test_edge_shapes_alpha_beta(gpu, dtype):
+    h, torch = gpu
+    cfgs = h.configs(dtype)
+    picks = [0, len(cfgs) // 3, len(cfgs) // 2, len(cfgs) - 1]
+    for (M, N, K, bt) in [(1, 1, 1, 1), (17, 31, 13, 1), (255, 257, 129, 1), (33, 1, 300, 3)]:
+        for (ta, tb) in synth.LAYOUTS:
+            a = synth.uniform_operand(M * 7 + ta, bt * M * K).reshape(bt, M, K)
+            b = synth.uniform_operand(N * 5 + tb, bt * K * N).reshape(bt, K, N)
+            c0 = synth.uniform_operand(99, bt * M * N).reshape(bt, M, N)
+            dA, dB, sA, sB, deq_a, deq_b = _prepare(h, torch, a, b, ta, tb, dtype)
+            for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
+                ref_q = _ref64(deq_a, deq_b, c0, alpha, beta)
+                tol = 1e-5 * math.sqrt(K) * abs(alpha) * np.abs(deq_a).max() * np.abs(deq_b).max() \
+                    + 2.0 ** -23 * np.abs(beta * c0)
+                for cfg in picks:
+                    c_init = np.full_like(c0, np.nan) if beta == 0 else c0
+                    got = _gemm(h, torch, dtype, dA, dB, sA, sB, K, ta, tb, alpha, beta, c_init, cfg)
+                    assert np.all(np.abs(got - ref_q) <= tol), (M, N, K, bt, ta, tb, alpha, cfgs[cfg])
+
+
+def test_odd_leading_dimension_scalar_path(gpu):
+    """BF16 rows with an odd leading dimension are not dword aligned and take
+    the element-wise load path."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    M, N, K = 40, 33, 27
+    a = synth.uniform_operand(3, M * K).reshape(1, M, K)
+    b = synth.uniform_operand(4, K * N).reshape(1, K, N)
+    dA, dB, _, _, deq_a, deq_b = _prepare(h, torch, a, b, 0, 0, BF16)
+    ref_q = _ref64(deq_a, deq_b, np.zeros((1, M, N), np.float32), 1.0, 0.0)
+    dC = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+    h.gemm_raw(BF16, kt.shape(M, N, K, 1, 0, 0), 1.0, dA, K, 0, dB, N, 0, 0.0, dC, N, 0, config_id=5)
+    torch.cuda.synchronize()
+    tol = 1e-5 * math.sqrt(K)
+    assert np.all(np.abs(dC.cpu().numpy() - ref_q[0]) <= tol)
+
+
+def test_lowp_sweep(gpu):
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    problems = [(256, 256, 256, 1, 0, 1), (100, 60, 70, 3, 1, 0)]
+    for dtype in (BF16, FP8):
+        ws_bytes = kt.Handle.sweep_workspace_bytes(problems, dtype)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        T = h.sweep(problems, ws, ws_bytes, config_ids=[0, 10, 30, 58], target_ms=0.2,
+                    max_reps=10, dtype=dtype)
+        assert (T > 0).all()
