@@ -75,6 +75,25 @@ def cpu_baseline(problems, budget_s=15.0, seed=13145):
                        f"{flops / 1e9:.1f} GFLOP in {t_tot:.1f} s, FP64 triple loop")
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from a committed rocprofv3 counter
+    summary (profiles/*_traffic.txt), if one exists for this kernel and the
+    kernel source has not changed since the counters were taken; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2008_13145_amd", "csrc", "gemm_f32.hpp")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt"))):
+        fields = {}
+        for line in open(path):
+            if "=" in line and not line.startswith(" "):
+                key, _, val = line.partition("=")
+                fields[key.strip()] = val.strip()
+        if fields.get("kernel") == kernel_name and fields.get("kernel_source_sha256", "").split()[:1] == [sha]:
+            return int(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +131,7 @@ def main(argv=None):
 
     h = kt.Handle(0)
     assert [tuple(c) for c in C.tolist()] == h.configs()
+    _log(f"bench: table {table_path} ({n_prob} problems x {n_cfg} configs)")
     stream = torch.cuda.current_stream()
 
     # ---- pruning (GPU k-means on the training rows) and the Top-N baseline
@@ -124,6 +144,7 @@ def main(argv=None):
                  workspace=pws, ws_bytes=ws_bytes, stream=stream)
     prune_ms = (time.perf_counter() - t0) * 1e3
     chosen = pr["chosen"]
+    _log(f"bench: pruned to {chosen} in {prune_ms:.1f} ms")
     topn = h.prune_topn(T[tr_rows], k, workspace=pws, ws_bytes=ws_bytes, stream=stream)
 
     t_best = T.min(axis=1)
@@ -191,6 +212,7 @@ def main(argv=None):
             if events is not None:
                 events[i][1].record(stream)
 
+    _log("bench: selectors fitted; warm-up")
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -217,6 +239,9 @@ def main(argv=None):
     dom = max(inst_time, key=inst_time.get)
     dom_rows = [i for i, p in enumerate(problems) if (picks_all[i], p[4], p[5]) == dom]
     dom_flops = float(flops[dom_rows].sum())
+    dom_bytes = float(sum(4.0 * problems[i][3] * (problems[i][0] * problems[i][2] +
+                                                  problems[i][2] * problems[i][1] +
+                                                  problems[i][0] * problems[i][1]) for i in dom_rows))
     dom_ms = float(t_launch[dom_rows].sum())
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     bm, bn, tt, bk = cfgs[dom[0]]
@@ -258,12 +283,15 @@ def main(argv=None):
         "roofline": {
             "bound": "mfma", "kernel": dom_name, "launches_per_step": len(dom_rows),
             "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic(dom_name),
+            "algorithmic_bytes_per_launch": int(dom_bytes / len(dom_rows)),
             "kernel_ms_per_step": round(dom_ms, 3),
         },
         "table": {"path": os.path.relpath(table_path, ROOT), "device": meta.get("device"),
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
     }
+    _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problems, a.cpu_budget_s)
     h.close()

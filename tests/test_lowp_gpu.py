@@ -3,8 +3,12 @@
 Accuracy bar: relative Frobenius error per result (per batch item) against
 the FP64 oracle on the original FP32 operands <= 1e-2 (BF16) and <= 4e-2
 (FP8).  The kernel itself is checked tighter against the oracle on the
-dequantized operands (FP32-accumulation bound), and bit for bit where every
-value and partial sum is exact."""
+dequantized operands: BF16 within the FP32-accumulation bound; FP8 within a
+relative Frobenius error of 1e-3, because gfx950's FP8 MFMA
+(v_mfma_f32_32x32x16_fp8_fp8) does not accumulate at full FP32 precision
+(measured: sums land on a grid of about 12 significant bits), and every FP8
+configuration must give the same bits.  BF16 is also checked bit for bit
+where every value and partial sum is exact."""
 import math
 
 import numpy as np
@@ -143,39 +147,63 @@ def test_all_configs_accuracy(gpu, dtype, ta, tb):
     bound = 1e-2 if dtype == BF16 else 4e-2
     tol_q = 1e-5 * math.sqrt(K) * np.abs(deq_a).max() * np.abs(deq_b).max()
     bad = []
-    worst = 0.0
+    first = None
     for cfg in range(h.num_configs(dtype)):
         got = _gemm(h, torch, dtype, dA, dB, sA, sB, K, ta, tb, alpha, beta,
                     np.full_like(c0, np.nan), cfg)
+        if first is None:
+            first = got
         for i in range(bt):
             e = cv.rel_frobenius(got[i], ref[i])
-            worst = max(worst, e)
-            if not e <= bound or not np.all(np.abs(got[i] - ref_q[i]) <= tol_q):
+            if dtype == BF16:
+                tight = bool(np.all(np.abs(got[i] - ref_q[i]) <= tol_q))
+            else:
+                tight = cv.rel_frobenius(got[i], ref_q[i]) <= 1e-3 and np.array_equal(got, first)
+            if not e <= bound or not tight:
                 bad.append((cfg, h.get_config(cfg, dtype), e))
     assert not bad, bad[:8]
 
 
-@pytest.mark.parametrize("dtype", [BF16, FP8])
 @pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
-def test_all_configs_exact_integers(gpu, dtype, ta, tb):
-    """Integers in [-7, 7]: exact in BF16, and exact in FP8 after the scale
-    448 / 7 = 64 (a power of two); all partial sums exact in FP32, so every
-    configuration equals the oracle bit for bit."""
+def test_all_configs_exact_integers_bf16(gpu, ta, tb):
+    """Integers in [-7, 7] are exact in BF16 and every partial sum is an
+    integer below 2^24, so every configuration equals the oracle bit for bit."""
     h, torch = gpu
     M, N, K, bt = 133, 96, 160, 2
     rng = np.random.default_rng(ta * 2 + tb)
     a = rng.integers(-7, 8, size=(bt, M, K)).astype(np.float32)
     b = rng.integers(-7, 8, size=(bt, K, N)).astype(np.float32)
+    c0 = np.zeros((bt, M, N), np.float32)
+    dA, dB, sA, sB, _, _ = _prepare(h, torch, a, b, ta, tb, BF16)
+    ref = _ref(a, b, c0, 1.0, 0.0)
+    bad = []
+    for cfg in range(h.num_configs(BF16)):
+        got = _gemm(h, torch, BF16, dA, dB, sA, sB, K, ta, tb, 1.0, 0.0, np.full_like(c0, np.nan), cfg)
+        if not np.array_equal(got.astype(np.float64), ref):
+            bad.append((cfg, h.get_config(cfg, BF16)))
+    assert not bad, bad[:8]
+
+
+@pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
+def test_fp8_one_mfma_block_exact(gpu, ta, tb):
+    """FP8 with K = 16 (one MFMA block) and values k * 64, k in [-7, 7]
+    (exact e4m3 codes after the power-of-two scale 448 / 7 = 64): the single
+    block's sum is exact, so every configuration equals the oracle."""
+    h, torch = gpu
+    M, N, K, bt = 70, 45, 16, 1
+    rng = np.random.default_rng(10 + ta * 2 + tb)
+    a = rng.integers(-7, 8, size=(bt, M, K)).astype(np.float32)
+    b = rng.integers(-7, 8, size=(bt, K, N)).astype(np.float32)
     a[:, 0, 0] = 7
     b[:, 0, 0] = -7
     c0 = np.zeros((bt, M, N), np.float32)
-    dA, dB, sA, sB, _, _ = _prepare(h, torch, a, b, ta, tb, dtype)
+    dA, dB, sA, sB, _, _ = _prepare(h, torch, a, b, ta, tb, FP8)
     ref = _ref(a, b, c0, 1.0, 0.0)
     bad = []
-    for cfg in range(h.num_configs(dtype)):
-        got = _gemm(h, torch, dtype, dA, dB, sA, sB, K, ta, tb, 1.0, 0.0, np.full_like(c0, np.nan), cfg)
+    for cfg in range(h.num_configs(FP8)):
+        got = _gemm(h, torch, FP8, dA, dB, sA, sB, K, ta, tb, 1.0, 0.0, np.full_like(c0, np.nan), cfg)
         if not np.array_equal(got.astype(np.float64), ref):
-            bad.append((cfg, h.get_config(cfg, dtype)))
+            bad.append((cfg, h.get_config(cfg, FP8), float(np.abs(got - ref).max())))
     assert not bad, bad[:8]
 
 
@@ -192,11 +220,14 @@ def test_edge_shapes_alpha_beta(gpu, dtype):
             dA, dB, sA, sB, deq_a, deq_b = _prepare(h, torch, a, b, ta, tb, dtype)
             for alpha, beta in ((1.0, 0.0), (-0.5, 2.0)):
                 ref_q = _ref64(deq_a, deq_b, c0, alpha, beta)
-                tol = 1e-5 * math.sqrt(K) * abs(alpha) * np.abs(deq_a).max() * np.abs(deq_b).max() \
+                # BF16: FP32-accumulation bound; FP8: the MFMA's ~12-bit accumulation
+                acc_rel = 1e-5 * math.sqrt(K) if dtype == BF16 else 2.0 ** -14 * K
+                tol = acc_rel * abs(alpha) * np.abs(deq_a).max() * np.abs(deq_b).max() \
                     + 2.0 ** -23 * np.abs(beta * c0)
                 for cfg in picks:
                     c_init = np.full_like(c0, np.nan) if beta == 0 else c0
                     got = _gemm(h, torch, dtype, dA, dB, sA, sB, K, ta, tb, alpha, beta, c_init, cfg)
+                    assert not np.isnan(got).any()
                     assert np.all(np.abs(got - ref_q) <= tol), (M, N, K, bt, ta, tb, alpha, cfgs[cfg])
 
 
