@@ -93,10 +93,13 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
   const int64_t tiles = cdiv(s->M, c.bm) * cdiv(s->N, c.bn);
   if (tiles > 0x7fffffffLL) return fail(h, KT_EINVAL, "problem too large for one grid");
   const int eb = elem_bytes(dtype);
-  // 16-byte vector loads need dword-aligned rows: pointer, leading dimension
-  // and batch stride all multiples of 4 bytes (FP32 always is).
-  auto aligned = [&](const void* p, int64_t ld, int64_t st) {
-    return ((uintptr_t)p % 4 == 0) && ((ld * eb) % 4 == 0) && ((st * eb) % 4 == 0);
+  // Row alignment of an operand for the low-precision loaders: 2 = every row
+  // starts on a 4-byte boundary, 1 = only the base pointer does (rows are then
+  // loaded through a realigned window), 0 = neither (element loads).  FP32
+  // rows are always 4-byte aligned.
+  auto aligned = [&](const void* p, int64_t ld, int64_t st) -> int32_t {
+    if ((uintptr_t)p % 4 != 0) return 0;
+    return ((ld * eb) % 4 == 0 && (st * eb) % 4 == 0) ? 2 : 1;
   };
   GemmArgs g;
   memset(&g, 0, sizeof g);

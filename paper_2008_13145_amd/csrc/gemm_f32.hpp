@@ -31,7 +31,7 @@ struct GemmArgs {
   float* C; int64_t ldc, sC;
   float alpha, beta;
   const float* scaleA; const float* scaleB;   // FP8 only
-  int32_t vecA, vecB;   // 16-byte aligned operands (pointer, ld, stride): low-precision paths
+  int32_t vecA, vecB;   // low-precision paths: row alignment mode (LP_ALIGN_*)
   int32_t tiles_m, tiles_n;
 };
 

@@ -11,10 +11,13 @@
 // 8-byte (FP8) LDS read.  Rows are padded by 16 bytes so the 32 rows a
 // half-wave reads start on different banks.  An operand stored contiguous
 // along K is copied into LDS with 16-byte vectors; one stored contiguous
-// along M / N is transposed element by element on the way in.
+// along M / N is transposed in registers, 8 K rows at a time, and written as
+// K-contiguous vectors.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "gemm_f32.hpp"
 
@@ -31,6 +34,28 @@ struct LpElem<2> { typedef uint16_t T; };
 template <>
 struct LpElem<1> { typedef uint8_t T; };
 
+// Operand alignment modes (GemmArgs::vecA / vecB for the low-precision
+// kernels): 2 = every row starts on a 4-byte boundary; 1 = only the operand's
+// base does (odd leading dimension or batch stride); 0 = unaligned base.
+enum { LP_ALIGN_NONE = 0, LP_ALIGN_BASE = 1, LP_ALIGN_ROWS = 2 };
+
+// WD dwords from byte address p, which need not be 4-byte aligned: the
+// dword-aligned window covering them (one dword more) is read and realigned
+// with v_alignbyte.  The caller guarantees that the window lies inside valid
+// memory (the window never starts below a 4-byte aligned base and its extra
+// bytes are columns of the same row).
+template <int WD>
+__device__ __forceinline__ void load_realigned(const void* p, uint32_t* out) {
+  const uintptr_t a = (uintptr_t)p;
+  const uint32_t mis = (uint32_t)(a & 3u);
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(a - mis);
+  uint32_t t[WD + 1];
+#pragma unroll
+  for (int d = 0; d <= WD; ++d) t[d] = w[d];
+#pragma unroll
+  for (int d = 0; d < WD; ++d) out[d] = __builtin_amdgcn_alignbyte(t[d + 1], t[d], mis);
+}
+
 // Global -> register staging of a ROWS x COLS tile (COLS contiguous in memory,
 // row stride ld elements), in 16-byte chunks.  Out-of-range elements read 0.
 template <int EB, int ROWS, int COLS, int NT>
@@ -44,9 +69,9 @@ struct LpTileLoader {
   u32x4 v[VPT];
 
   __device__ __forceinline__ void load(const E* __restrict__ base, int64_t ld, int64_t row0,
-                                       int64_t col0, int64_t row_lim, int64_t col_lim, bool vec,
+                                       int64_t col0, int64_t row_lim, int64_t col_lim, int vec,
                                        int tid) {
-    const bool full = vec && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
+    const bool full = vec == LP_ALIGN_ROWS && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int c = tid + i * NT;
@@ -59,8 +84,12 @@ struct LpTileLoader {
       } else {
         u32x4 t = {0u, 0u, 0u, 0u};
         if (gr < row_lim) {
-          if (vec && gc + EPC <= col_lim) {
+          if (vec == LP_ALIGN_ROWS && gc + EPC <= col_lim) {
             t = *reinterpret_cast<const u32x4u*>(p);
+          } else if (vec == LP_ALIGN_BASE && gc + EPC + 4 / EB <= col_lim) {
+            uint32_t o[4];
+            load_realigned<4>(p, o);
+            t = u32x4{o[0], o[1], o[2], o[3]};
           } else {
             // element by element, packed little-endian into the chunk
 #pragma unroll
@@ -90,6 +119,95 @@ struct LpTileLoader {
           lds[(q + e) * LD + r] = (E)(v[i][(e * EB) / 4] >> (8 * ((e * EB) % 4)));
       } else {
         *reinterpret_cast<u32x4*>(lds + r * LD + q) = v[i];
+      }
+    }
+  }
+};
+
+// Staging of a K x COLS tile whose COLS dimension is contiguous in memory
+// (op(A) stored K x M, or op(B) stored K x N), for an LDS layout with K
+// contiguous ([col][k]).  Each unit is 8 rows of K by a W-byte chunk of
+// columns (W = 4, 8 or 16, sized so the units spread over all threads): the
+// 8 chunks are loaded (coalesced along the columns), transposed in registers
+// with byte permutes, and written as one 8-deep K run per column (16 bytes
+// for BF16, 8 bytes for FP8).
+template <int EB, int KROWS, int COLS, int NT>
+struct LpTransposeLoader {
+  typedef typename LpElem<EB>::T E;
+  static constexpr int TILE_BYTES = KROWS * COLS * EB;
+  static constexpr int W = (TILE_BYTES >= 8 * 16 * NT) ? 16 : (TILE_BYTES >= 8 * 8 * NT) ? 8 : 4;
+  static constexpr int WD = W / 4;                    // dwords per row chunk
+  static constexpr int EPC = W / EB;                  // columns per unit
+  static constexpr int CU = COLS / EPC;               // units across the columns
+  static constexpr int NU = (KROWS / 8) * CU;         // units in the tile
+  static constexpr int UPT = (NU + NT - 1) / NT;
+  static_assert(KROWS % 8 == 0 && COLS % EPC == 0, "tile must hold whole units");
+  uint32_t v[UPT][8][WD];
+
+  __device__ __forceinline__ void load(const E* __restrict__ base, int64_t ld, int64_t k0,
+                                       int64_t col0, int64_t k_lim, int64_t col_lim, int vec,
+                                       int tid) {
+    const bool full = vec == LP_ALIGN_ROWS && (k0 + KROWS <= k_lim) && (col0 + COLS <= col_lim);
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int u = tid + i * NT;
+      if (NU % NT != 0 && u >= NU) continue;
+      const int ku = u / CU, cu = u % CU;
+      const int64_t gc = col0 + cu * EPC;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t gk = k0 + ku * 8 + r;
+        const E* p = base + gk * ld + gc;
+        const bool in_rows = gk < k_lim;
+        if (full || (vec == LP_ALIGN_ROWS && in_rows && gc + EPC <= col_lim)) {
+#pragma unroll
+          for (int d = 0; d < WD; ++d) v[i][r][d] = reinterpret_cast<const uint32_t*>(p)[d];
+        } else if (vec == LP_ALIGN_BASE && in_rows && gc + EPC + 4 / EB <= col_lim) {
+          load_realigned<WD>(p, v[i][r]);
+        } else {
+#pragma unroll
+          for (int d = 0; d < WD; ++d) v[i][r][d] = 0u;
+          if (in_rows) {
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+              const uint32_t x = (gc + e < col_lim) ? (uint32_t)p[e] : 0u;
+              v[i][r][(e * EB) / 4] |= x << (8 * ((e * EB) % 4));
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // lds is [COLS][LD] with K contiguous; the tile's K rows start at k = 0.
+  template <int LD>
+  __device__ __forceinline__ void store(E* lds, int tid) const {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+      const int u = tid + i * NT;
+      if (NU % NT != 0 && u >= NU) continue;
+      const int ku = u / CU, cu = u % CU;
+#pragma unroll
+      for (int c = 0; c < EPC; ++c) {
+        const int d = (c * EB) / 4;
+        if (EB == 2) {
+          // dword j of column c = (row 2j, row 2j + 1) elements c
+          const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+          u32x4 out;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) out[j] = __builtin_amdgcn_perm(v[i][2 * j + 1][d], v[i][2 * j][d], sel);
+          *reinterpret_cast<u32x4*>(lds + (cu * EPC + c) * LD + ku * 8) = out;
+        } else {
+          // dword h of column c = bytes c of rows 4h .. 4h + 3
+          const int sh = 8 * (c & 3);
+          uint32_t w[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            w[h] = ((v[i][4 * h + 0][d] >> sh) & 0xFFu) | (((v[i][4 * h + 1][d] >> sh) & 0xFFu) << 8) |
+                   (((v[i][4 * h + 2][d] >> sh) & 0xFFu) << 16) | (((v[i][4 * h + 3][d] >> sh) & 0xFFu) << 24);
+          typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+          *reinterpret_cast<u32x2*>(lds + (cu * EPC + c) * LD + ku * 8) = u32x2{w[0], w[1]};
+        }
       }
     }
   }
@@ -155,11 +273,16 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
   const int64_t M = args.M, N = args.N, K = args.K;
   const E* __restrict__ Ag = static_cast<const E*>(args.A) + bz * args.sA;
   const E* __restrict__ Bg = static_cast<const E*>(args.B) + bz * args.sB;
-  const bool vecA = args.vecA != 0, vecB = args.vecB != 0;
+  const int vecA = args.vecA, vecB = args.vecB;
 
-  // A: TA == 0 -> k contiguous (direct), TA == 1 -> m contiguous (transpose).
-  LpTileLoader<EB, (TA ? BK : BM), (TA ? BM : BK), NT> la;
-  LpTileLoader<EB, (TB ? BN : BK), (TB ? BK : BN), NT> lb;
+  // A: TA == 0 -> k contiguous (direct 16-byte copy), TA == 1 -> m contiguous
+  // (register transpose).  B: TB == 1 -> direct, TB == 0 -> transpose.
+  typedef typename std::conditional<TA == 0, LpTileLoader<EB, BM, BK, NT>,
+                                    LpTransposeLoader<EB, BK, BM, NT>>::type LoaderA;
+  typedef typename std::conditional<TB == 1, LpTileLoader<EB, BN, BK, NT>,
+                                    LpTransposeLoader<EB, BK, BN, NT>>::type LoaderB;
+  LoaderA la;
+  LoaderB lb;
 
   auto load_stage = [&](int64_t k0) {
     if (TA) la.load(Ag, args.lda, k0, m0, K, M, vecA, tid);
@@ -168,8 +291,10 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
     else    lb.load(Bg, args.ldb, k0, n0, K, N, vecB, tid);
   };
   auto store_stage = [&](int buf) {
-    la.template store<TA == 1, LDK>(As + buf * Cfg::A_STAGE, tid);
-    lb.template store<TB == 0, LDK>(Bs + buf * Cfg::B_STAGE, tid);
+    if constexpr (TA == 0) la.template store<false, LDK>(As + buf * Cfg::A_STAGE, tid);
+    else                   la.template store<LDK>(As + buf * Cfg::A_STAGE, tid);
+    if constexpr (TB == 1) lb.template store<false, LDK>(Bs + buf * Cfg::B_STAGE, tid);
+    else                   lb.template store<LDK>(Bs + buf * Cfg::B_STAGE, tid);
   };
 
   f32x16 acc[SUB][SUB];

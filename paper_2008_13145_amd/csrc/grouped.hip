@@ -161,8 +161,8 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
     d.A = A[i]; d.B = B[i]; d.C = C[i];
     d.M = s.M; d.N = s.N; d.K = s.K;
     d.lda = std::max<int64_t>(s.K, 1); d.ldb = std::max<int64_t>(s.N, 1); d.ldc = std::max<int64_t>(s.N, 1);
-    d.vecA = ((uintptr_t)A[i] % 4 == 0) && (d.lda % 2 == 0);
-    d.vecB = ((uintptr_t)B[i] % 4 == 0) && (d.ldb % 2 == 0);
+    d.vecA = ((uintptr_t)A[i] % 4 != 0) ? 0 : (d.lda % 2 == 0 ? 2 : 1);
+    d.vecB = ((uintptr_t)B[i] % 4 != 0) ? 0 : (d.ldb % 2 == 0 ? 2 : 1);
   }
   std::vector<int32_t> gorder(n);
   std::iota(gorder.begin(), gorder.end(), 0);

@@ -231,21 +231,42 @@ def test_edge_shapes_alpha_beta(gpu, dtype):
                     assert np.all(np.abs(got - ref_q) <= tol), (M, N, K, bt, ta, tb, alpha, cfgs[cfg])
 
 
-def test_odd_leading_dimension_scalar_path(gpu):
-    """BF16 rows with an odd leading dimension are not dword aligned and take
-    the element-wise load path."""
+@pytest.mark.parametrize("dtype", [BF16, FP8])
+@pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
+def test_unaligned_rows_and_bases(gpu, dtype, ta, tb):
+    """Leading dimensions that leave rows off 4-byte boundaries take the
+    realigned-window loads; a base pointer off a 4-byte boundary takes the
+    element loads.  Both must match the dense reference."""
     import paper_2008_13145_amd as kt
     h, torch = gpu
-    M, N, K = 40, 33, 27
-    a = synth.uniform_operand(3, M * K).reshape(1, M, K)
-    b = synth.uniform_operand(4, K * N).reshape(1, K, N)
-    dA, dB, _, _, deq_a, deq_b = _prepare(h, torch, a, b, 0, 0, BF16)
-    ref_q = _ref64(deq_a, deq_b, np.zeros((1, M, N), np.float32), 1.0, 0.0)
-    dC = torch.zeros((M, N), dtype=torch.float32, device="cuda")
-    h.gemm_raw(BF16, kt.shape(M, N, K, 1, 0, 0), 1.0, dA, K, 0, dB, N, 0, 0.0, dC, N, 0, config_id=5)
-    torch.cuda.synchronize()
-    tol = 1e-5 * math.sqrt(K)
-    assert np.all(np.abs(dC.cpu().numpy() - ref_q[0]) <= tol)
+    M, N, K = 75, 61, 53
+    a = synth.uniform_operand(3 + ta, M * K).reshape(1, M, K)
+    b = synth.uniform_operand(4 + tb, K * N).reshape(1, K, N)
+    _, _, sA, sB, deq_a, deq_b = _prepare(h, torch, a, b, ta, tb, dtype)
+    qa = cv.bf16_rne(a) if dtype == BF16 else cv.quantize_fp8(a)[0]
+    qb = cv.bf16_rne(b) if dtype == BF16 else cv.quantize_fp8(b)[0]
+    As, Bs = _stored(qa, ta)[0], _stored(qb, tb)[0]
+    ref_q = _ref64(deq_a, deq_b, np.zeros((1, M, N), np.float32), 1.0, 0.0)[0]
+    acc_rel = 1e-5 * math.sqrt(K) if dtype == BF16 else 2.0 ** -14 * K
+    tol = acc_rel * np.abs(deq_a).max() * np.abs(deq_b).max()
+    tdt = torch.int16 if dtype == BF16 else torch.uint8
+    eb = 2 if dtype == BF16 else 1
+    cfgs = h.configs(dtype)
+    for pad_a, pad_b, off in ((1, 3, 0), (0, 0, 1), (5, 2, 2)):
+        lda, ldb = As.shape[1] + pad_a, Bs.shape[1] + pad_b
+        bufA = torch.zeros(off + As.shape[0] * lda + 8, dtype=tdt, device="cuda")
+        bufB = torch.zeros(off + Bs.shape[0] * ldb + 8, dtype=tdt, device="cuda")
+        bufA[off:off + As.shape[0] * lda].view(As.shape[0], lda)[:, :As.shape[1]] = \
+            torch.from_numpy(As.view(np.int16) if dtype == BF16 else As).cuda()
+        bufB[off:off + Bs.shape[0] * ldb].view(Bs.shape[0], ldb)[:, :Bs.shape[1]] = \
+            torch.from_numpy(Bs.view(np.int16) if dtype == BF16 else Bs).cuda()
+        for cfg in (0, 17, 40, len(cfgs) - 1):
+            dC = torch.zeros((M, N), dtype=torch.float32, device="cuda")
+            h.gemm_raw(dtype, kt.shape(M, N, K, 1, ta, tb), 1.0, bufA.data_ptr() + off * eb, lda, 0,
+                       bufB.data_ptr() + off * eb, ldb, 0, 0.0, dC, N, 0, scaleA=sA, scaleB=sB,
+                       config_id=cfg)
+            torch.cuda.synchronize()
+            assert np.all(np.abs(dC.cpu().numpy() - ref_q) <= tol), (pad_a, pad_b, off, cfgs[cfg])
 
 
 def test_lowp_sweep(gpu):
