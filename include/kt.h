@@ -230,7 +230,10 @@ typedef struct {
                              0 or 1: launch every step directly */
 } kt_mlp_opts;
 
-/* Fit the runtime selector on n_rows problems (section 5.1).  shapes and
+/* Fit the runtime selector of one dtype on n_rows problems (section 5.1);
+ * each dtype (its own configuration space and sweep table) has its own
+ * selector, and kt_gemm(config_id = -1) asks the one of its input dtype.
+ * shapes and
  * time_ns are host arrays; chosen[k] are the deployed configuration ids.
  * Each row is labelled with the fastest chosen configuration (lowest
  * position on equal times).  Decision trees are fitted on the host (integer
@@ -238,7 +241,7 @@ typedef struct {
  * thresholds floor(sqrt(a*b)) between consecutive values; x <= t goes left).
  * KT_SEL_MLP trains the cost model on the GPU (needs a device handle and a
  * workspace of kt_mlp_workspace_bytes).  KT_SEL_EXHAUSTIVE needs no data. */
-kt_status kt_fit_selector(kt_handle h, kt_selector sel, const kt_shape* shapes,
+kt_status kt_fit_selector(kt_handle h, kt_dtype dtype, kt_selector sel, const kt_shape* shapes,
                           const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
                           const int32_t* chosen, int32_t k, const kt_mlp_opts* mlp,
                           void* workspace, size_t ws_bytes, void* stream);
@@ -247,20 +250,20 @@ kt_status kt_fit_selector(kt_handle h, kt_selector sel, const kt_shape* shapes,
  * except for KT_SEL_EXHAUSTIVE, which times every compiled configuration for
  * an unseen shape once (on scratch buffers the handle allocates) and caches
  * the winner. */
-kt_status kt_select(kt_handle h, const kt_shape* s, int32_t* config_id);
+kt_status kt_select(kt_handle h, kt_dtype dtype, const kt_shape* s, int32_t* config_id);
 
 /* Same for n shapes on the device: d_shapes and d_ids are device arrays. */
-kt_status kt_select_batch(kt_handle h, const kt_shape* d_shapes, int32_t n, int32_t* d_ids,
-                          void* stream);
+kt_status kt_select_batch(kt_handle h, kt_dtype dtype, const kt_shape* d_shapes, int32_t n,
+                          int32_t* d_ids, void* stream);
 
 /* Inspect the fitted tree: node arrays in pre-order (left child first);
  * feature = -1 marks a leaf, whose class indexes `chosen`.  Pass NULL arrays
  * to query *n_nodes only. */
-kt_status kt_get_tree(kt_handle h, int32_t* n_nodes, int32_t* feature, int64_t* threshold,
-                      int32_t* left, int32_t* right, int32_t* cls);
+kt_status kt_get_tree(kt_handle h, kt_dtype dtype, int32_t* n_nodes, int32_t* feature,
+                      int64_t* threshold, int32_t* left, int32_t* right, int32_t* cls);
 
-/* Save / load the selector state (kind, chosen ids, tree or MLP weights) as
- * a versioned text file.  kt_load returns KT_EIO for a missing or malformed
+/* Save / load the selectors of every dtype that has one (kind, chosen ids,
+ * tree or MLP weights) as a versioned text file.  kt_load returns KT_EIO for a missing or malformed
  * file and leaves the handle unchanged in that case. */
 kt_status kt_save(kt_handle h, const char* path);
 kt_status kt_load(kt_handle h, const char* path);
@@ -340,7 +343,7 @@ kt_status kt_mlp_forward_backward(kt_handle h, const float* d_params, const floa
                                   float* d_grad, float* d_loss, void* workspace, size_t ws_bytes,
                                   void* stream);
 /* Copy the fitted MLP parameters (host).  NULL params queries *n_params. */
-kt_status kt_get_mlp(kt_handle h, int32_t* n_params, float* params);
+kt_status kt_get_mlp(kt_handle h, kt_dtype dtype, int32_t* n_params, float* params);
 
 #ifdef __cplusplus
 }

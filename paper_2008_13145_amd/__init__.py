@@ -83,11 +83,11 @@ _SIGS = {
     "kt_prune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                          c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
     "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp, c_vp]),
-    "kt_fit_selector": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp, c_i32,
-                                ctypes.POINTER(MlpOpts), c_vp, c_sz, c_vp]),
-    "kt_select": (c_i32, [c_vp, ctypes.POINTER(Shape), ctypes.POINTER(c_i32)]),
-    "kt_select_batch": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
-    "kt_get_tree": (c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "kt_fit_selector": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp,
+                                c_i32, ctypes.POINTER(MlpOpts), c_vp, c_sz, c_vp]),
+    "kt_select": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), ctypes.POINTER(c_i32)]),
+    "kt_select_batch": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_vp, c_vp]),
+    "kt_get_tree": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp]),
     "kt_save": (c_i32, [c_vp, ctypes.c_char_p]),
     "kt_load": (c_i32, [c_vp, ctypes.c_char_p]),
     "kt_grouped_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
@@ -108,7 +108,7 @@ _SIGS = {
     "kt_mlp_features": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
     "kt_mlp_forward_backward": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp,
                                         c_vp, c_sz, c_vp]),
-    "kt_get_mlp": (c_i32, [c_vp, ctypes.POINTER(c_i32), c_vp]),
+    "kt_get_mlp": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32), c_vp]),
 }
 
 _lib = None
@@ -332,7 +332,7 @@ class Handle:
     # ------------------------------------------------------------- select
     def fit_selector(self, kind, shapes, time_ns, chosen, mlp_steps=3000, mlp_lr=1e-3,
                      mlp_init=None, mlp_seed=13150, mlp_graph_steps=25, workspace=None, ws_bytes=0,
-                     stream=None):
+                     stream=None, dtype=F32):
         arr = shapes_array(shapes)
         T = np.ascontiguousarray(time_ns, dtype=np.int64)
         ch = np.ascontiguousarray(chosen, dtype=np.int32)
@@ -344,32 +344,33 @@ class Handle:
                 keep = np.ascontiguousarray(mlp_init, dtype=np.float32)
                 init_ptr = keep.ctypes.data_as(ctypes.POINTER(c_f32))
             opts = MlpOpts(int(mlp_steps), float(mlp_lr), init_ptr, int(mlp_seed), int(mlp_graph_steps))
-        self._check(self.L.kt_fit_selector(self.h, int(kind), arr, T.ctypes.data, T.shape[0],
+        self._check(self.L.kt_fit_selector(self.h, int(dtype), int(kind), arr, T.ctypes.data, T.shape[0],
                                            T.shape[1], ch.ctypes.data, len(ch),
                                            None if opts is None else ctypes.byref(opts),
                                            _ptr(workspace), int(ws_bytes), _stream(stream)))
         del keep
 
-    def select(self, M, N, K, batch=1, transA=0, transB=0) -> int:
+    def select(self, M, N, K, batch=1, transA=0, transB=0, dtype=F32) -> int:
         v = c_i32()
         s = shape(M, N, K, batch, transA, transB)
-        self._check(self.L.kt_select(self.h, ctypes.byref(s), ctypes.byref(v)))
+        self._check(self.L.kt_select(self.h, int(dtype), ctypes.byref(s), ctypes.byref(v)))
         return v.value
 
-    def select_batch(self, d_shapes, n, d_ids, stream=None):
-        self._check(self.L.kt_select_batch(self.h, _ptr(d_shapes), int(n), _ptr(d_ids),
+    def select_batch(self, d_shapes, n, d_ids, stream=None, dtype=F32):
+        self._check(self.L.kt_select_batch(self.h, int(dtype), _ptr(d_shapes), int(n), _ptr(d_ids),
                                            _stream(stream)))
 
-    def get_tree(self):
+    def get_tree(self, dtype=F32):
         n = c_i32()
-        self._check(self.L.kt_get_tree(self.h, ctypes.byref(n), None, None, None, None, None))
+        self._check(self.L.kt_get_tree(self.h, int(dtype), ctypes.byref(n), None, None, None, None,
+                                       None))
         f = np.zeros(n.value, np.int32)
         t = np.zeros(n.value, np.int64)
         l = np.zeros(n.value, np.int32)
         r = np.zeros(n.value, np.int32)
         c = np.zeros(n.value, np.int32)
-        self._check(self.L.kt_get_tree(self.h, ctypes.byref(n), f.ctypes.data, t.ctypes.data,
-                                       l.ctypes.data, r.ctypes.data, c.ctypes.data))
+        self._check(self.L.kt_get_tree(self.h, int(dtype), ctypes.byref(n), f.ctypes.data,
+                                       t.ctypes.data, l.ctypes.data, r.ctypes.data, c.ctypes.data))
         return dict(feature=f.tolist(), threshold=t.tolist(), left=l.tolist(), right=r.tolist(),
                     cls=c.tolist())
 
@@ -406,11 +407,11 @@ class Handle:
                                                    _ptr(d_loss), _ptr(workspace), int(ws_bytes),
                                                    _stream(stream)))
 
-    def get_mlp(self):
+    def get_mlp(self, dtype=F32):
         n = c_i32()
-        self._check(self.L.kt_get_mlp(self.h, ctypes.byref(n), None))
+        self._check(self.L.kt_get_mlp(self.h, int(dtype), ctypes.byref(n), None))
         out = np.zeros(n.value, dtype=np.float32)
-        self._check(self.L.kt_get_mlp(self.h, ctypes.byref(n), out.ctypes.data))
+        self._check(self.L.kt_get_mlp(self.h, int(dtype), ctypes.byref(n), out.ctypes.data))
         return out
 
     # ------------------------------------------------------------ grouped

@@ -176,8 +176,7 @@ kt_status kt_destroy(kt_handle hh) {
   if (!h) return KT_OK;
   if (h->device >= 0) {
     (void)hipSetDevice(h->device);
-    if (h->d_tree) (void)hipFree(h->d_tree);
-    if (h->d_mlp) (void)hipFree(h->d_mlp);
+    for (int d = 0; d < NUM_DTYPES; ++d) free_selector_device(h, d);
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->d_lut) (void)hipFree(h->d_lut);
   }
@@ -233,7 +232,7 @@ kt_status kt_gemm(kt_handle hh, kt_dtype in_dtype, const kt_shape* s, float alph
     return fail(h, KT_EINVAL, "FP8 needs device scale pointers");
   int32_t cfg = config_id;
   if (cfg < 0) {
-    st = select_config(h, s, &cfg);
+    st = select_config(h, in_dtype, s, &cfg);
     if (st != KT_OK) return st;
   }
   if (cfg >= (int32_t)h->configs[in_dtype].size())

@@ -34,22 +34,26 @@ struct ShapeKey {
   }
 };
 
+// Selector state of one dtype (each dtype has its own configuration space,
+// sweep table, pruned set and selector).
+struct SelState {
+  int32_t kind = -1;               // kt_selector, -1 = none
+  std::vector<int32_t> chosen;     // deployed configuration ids
+  Tree tree;
+  MlpModel mlp;
+  void* d_tree = nullptr;          // device copy of the tree for batch selection
+  size_t d_tree_bytes = 0;
+  void* d_mlp = nullptr;           // device copy of the MLP weights + chosen ids
+  std::map<ShapeKey, int32_t> exhaustive_cache;
+};
+
 struct Ctx {
   int device = -1;
   std::string err;
   // launcher lookup: [dtype][id * 4 + layout]
   std::vector<LaunchFn> table[NUM_DTYPES];
   std::vector<ConfigDef> configs[NUM_DTYPES];
-  // selector state
-  int32_t sel_kind = -1;           // kt_selector, -1 = none
-  std::vector<int32_t> chosen;     // deployed configuration ids
-  int32_t sel_dtype = KT_F32;
-  Tree tree;
-  MlpModel mlp;
-  void* d_tree = nullptr;          // device copy of the tree for batch selection
-  size_t d_tree_bytes = 0;
-  void* d_mlp = nullptr;
-  std::map<ShapeKey, int32_t> exhaustive_cache;
+  SelState sel[NUM_DTYPES];
   void* scratch = nullptr;         // exhaustive-selection operands (handle-owned)
   size_t scratch_bytes = 0;
   std::vector<uint16_t> sigmoid_lut;
@@ -77,14 +81,16 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
 // Fill kernel launcher (device).
 hipError_t fill_uniform(float* dst, int64_t n, uint64_t seed, int64_t offset, hipStream_t s);
 
-// Selector helpers (select.hip, mlp.hip).
-kt_status select_config(Ctx* h, const kt_shape* s, int32_t* id);
-kt_status mlp_select_host(Ctx* h, const kt_shape* s, int32_t* id);
-kt_status mlp_select_batch(Ctx* h, const kt_shape* d_shapes, int32_t n, int32_t* d_ids, hipStream_t st);
-kt_status mlp_upload(Ctx* h);
-kt_status fit_mlp(Ctx* h, const kt_shape* shapes, const int64_t* time_ns, int32_t n, int32_t d,
-                  const int32_t* chosen, int32_t k, const kt_mlp_opts* o, void* ws, size_t ws_bytes,
-                  hipStream_t st);
+// Selector helpers (select.hip, mlp.hip); dtype picks the selector state.
+kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id);
+kt_status mlp_select_host(Ctx* h, int dtype, const kt_shape* s, int32_t* id);
+kt_status mlp_select_batch(Ctx* h, int dtype, const kt_shape* d_shapes, int32_t n, int32_t* d_ids,
+                           hipStream_t st);
+kt_status mlp_upload(Ctx* h, int dtype);
+kt_status fit_mlp(Ctx* h, int dtype, const kt_shape* shapes, const int64_t* time_ns, int32_t n,
+                  int32_t d, const int32_t* chosen, int32_t k, const kt_mlp_opts* o, void* ws,
+                  size_t ws_bytes, hipStream_t st);
+void free_selector_device(Ctx* h, int dtype);
 
 // Sigmoid lookup table of the normalization (Q16 -> Q16).
 const std::vector<uint16_t>& sigmoid_table(Ctx* h);

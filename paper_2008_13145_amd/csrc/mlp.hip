@@ -325,24 +325,27 @@ static void he_uniform(std::vector<float>& P, int k, uint64_t seed) {
   fill(L.oW3, k, MLP_H);
 }
 
-kt_status mlp_upload(Ctx* h) {
+kt_status mlp_upload(Ctx* h, int dtype) {
+  SelState& S = h->sel[dtype];
   if (h->device < 0) return KT_OK;
-  if (h->d_mlp) { (void)hipFree(h->d_mlp); h->d_mlp = nullptr; }
-  const size_t pbytes = h->mlp.params.size() * 4, cbytes = h->chosen.size() * 4;
-  hipError_t e = hipMalloc(&h->d_mlp, pbytes + cbytes + 256);
-  if (e != hipSuccess) { h->d_mlp = nullptr; return hip_fail(h, e, "hipMalloc MLP weights"); }
-  e = hipMemcpy(h->d_mlp, h->mlp.params.data(), pbytes, hipMemcpyHostToDevice);
+  if (S.d_mlp) { (void)hipFree(S.d_mlp); S.d_mlp = nullptr; }
+  const size_t pbytes = S.mlp.params.size() * 4, cbytes = S.chosen.size() * 4;
+  hipError_t e = hipMalloc(&S.d_mlp, pbytes + cbytes + 256);
+  if (e != hipSuccess) { S.d_mlp = nullptr; return hip_fail(h, e, "hipMalloc MLP weights"); }
+  e = hipMemcpy(S.d_mlp, S.mlp.params.data(), pbytes, hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy((char*)h->d_mlp + pbytes, h->chosen.data(), cbytes, hipMemcpyHostToDevice);
+    e = hipMemcpy((char*)S.d_mlp + pbytes, S.chosen.data(), cbytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "upload MLP weights");
   return KT_OK;
 }
 
-kt_status mlp_select_batch(Ctx* h, const kt_shape* d_shapes, int32_t n, int32_t* d_ids, hipStream_t st) {
-  if (!h->d_mlp) return fail(h, KT_ENOTFITTED, "MLP weights not on the device");
-  const int k = h->mlp.k;
-  const float* P = (const float*)h->d_mlp;
-  const int32_t* chosen = (const int32_t*)((const char*)h->d_mlp + h->mlp.params.size() * 4);
+kt_status mlp_select_batch(Ctx* h, int dtype, const kt_shape* d_shapes, int32_t n, int32_t* d_ids,
+                           hipStream_t st) {
+  SelState& S = h->sel[dtype];
+  if (!S.d_mlp) return fail(h, KT_ENOTFITTED, "MLP weights not on the device");
+  const int k = S.mlp.k;
+  const float* P = (const float*)S.d_mlp;
+  const int32_t* chosen = (const int32_t*)((const char*)S.d_mlp + S.mlp.params.size() * 4);
   hipLaunchKernelGGL(mlp_select_kernel, dim3((n + 63) / 64), dim3(64), 0, st, d_shapes, n, P, k,
                      chosen, d_ids);
   hipError_t e = hipGetLastError();
@@ -350,24 +353,25 @@ kt_status mlp_select_batch(Ctx* h, const kt_shape* d_shapes, int32_t n, int32_t*
   return KT_OK;
 }
 
-kt_status mlp_select_host(Ctx* h, const kt_shape* s, int32_t* id) {
+kt_status mlp_select_host(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
+  SelState& S = h->sel[dtype];
   if (!need_device(h)) return KT_EINVAL;
-  if (!h->d_mlp) return fail(h, KT_ENOTFITTED, "MLP weights not on the device");
+  if (!S.d_mlp) return fail(h, KT_ENOTFITTED, "MLP weights not on the device");
   // a 64-byte staging area past the chosen ids holds the shape and the answer
-  char* base = (char*)h->d_mlp + h->mlp.params.size() * 4 + h->chosen.size() * 4;
+  char* base = (char*)S.d_mlp + S.mlp.params.size() * 4 + S.chosen.size() * 4;
   base = (char*)(((uintptr_t)base + 15) & ~(uintptr_t)15);
   hipError_t e = hipMemcpy(base, s, sizeof(kt_shape), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "upload shape");
-  kt_status r = mlp_select_batch(h, (const kt_shape*)base, 1, (int32_t*)(base + 64), nullptr);
+  kt_status r = mlp_select_batch(h, dtype, (const kt_shape*)base, 1, (int32_t*)(base + 64), nullptr);
   if (r != KT_OK) return r;
   e = hipMemcpy(id, base + 64, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(h, e, "read selection");
   return KT_OK;
 }
 
-kt_status fit_mlp(Ctx* h, const kt_shape* shapes, const int64_t* time_ns, int32_t n, int32_t d,
-                  const int32_t* chosen, int32_t k, const kt_mlp_opts* o, void* ws, size_t ws_bytes,
-                  hipStream_t st) {
+kt_status fit_mlp(Ctx* h, int dtype, const kt_shape* shapes, const int64_t* time_ns, int32_t n,
+                  int32_t d, const int32_t* chosen, int32_t k, const kt_mlp_opts* o, void* ws,
+                  size_t ws_bytes, hipStream_t st) {
   if (!need_device(h)) return KT_EINVAL;
   if (k > MLP_MAX_K) return fail(h, KT_EINVAL, "MLP supports k <= 64");
   kt_mlp_opts opts = {3000, 1e-3f, nullptr, 13150, 25};
@@ -440,14 +444,17 @@ kt_status fit_mlp(Ctx* h, const kt_shape* shapes, const int64_t* time_ns, int32_
   }
   for (; done < opts.steps; ++done)
     if ((e = one_step(st)) != hipSuccess) return hip_fail(h, e, "MLP training step");
-  h->mlp.k = k;
-  h->mlp.params.resize(L.total);
-  e = hipMemcpyAsync(h->mlp.params.data(), P, (size_t)L.total * 4, hipMemcpyDeviceToHost, st);
+  std::vector<float> trained(L.total);
+  e = hipMemcpyAsync(trained.data(), P, (size_t)L.total * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(h, e, "read MLP weights");
-  std::vector<int32_t> keep_chosen(chosen, chosen + k);
-  h->chosen = keep_chosen;
-  return mlp_upload(h);
+  free_selector_device(h, dtype);
+  SelState& S = h->sel[dtype];
+  S = SelState();
+  S.mlp.k = k;
+  S.mlp.params = std::move(trained);
+  S.chosen.assign(chosen, chosen + k);
+  return mlp_upload(h, dtype);
 }
 
 }  // namespace kt
@@ -513,13 +520,15 @@ kt_status kt_mlp_forward_backward(kt_handle hh, const float* d_params, const flo
   return KT_OK;
 }
 
-kt_status kt_get_mlp(kt_handle hh, int32_t* n_params, float* params) {
+kt_status kt_get_mlp(kt_handle hh, kt_dtype dtype, int32_t* n_params, float* params) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
   if (!n_params) return fail(h, KT_EINVAL, "NULL n_params");
-  if (h->sel_kind != KT_SEL_MLP) return fail(h, KT_ENOTFITTED, "no MLP fitted");
-  *n_params = (int32_t)h->mlp.params.size();
-  if (params) memcpy(params, h->mlp.params.data(), h->mlp.params.size() * 4);
+  const SelState& S = h->sel[dtype];
+  if (S.kind != KT_SEL_MLP) return fail(h, KT_ENOTFITTED, "no MLP fitted");
+  *n_params = (int32_t)S.mlp.params.size();
+  if (params) memcpy(params, S.mlp.params.data(), S.mlp.params.size() * 4);
   return KT_OK;
 }
 

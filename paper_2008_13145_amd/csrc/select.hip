@@ -158,42 +158,60 @@ __global__ void select_tree_kernel(const kt_shape* __restrict__ shapes, int32_t 
   ids[i] = (c >= 0 && c < k) ? chosen[c] : -1;
 }
 
-static kt_status upload_tree(Ctx* h) {
+void free_selector_device(Ctx* h, int dtype) {
+  SelState& S = h->sel[dtype];
+  if (h->device >= 0) {
+    if (S.d_tree) (void)hipFree(S.d_tree);
+    if (S.d_mlp) (void)hipFree(S.d_mlp);
+  }
+  S.d_tree = nullptr;
+  S.d_tree_bytes = 0;
+  S.d_mlp = nullptr;
+}
+
+static kt_status upload_tree(Ctx* h, int dtype) {
+  SelState& S = h->sel[dtype];
   if (h->device < 0) return KT_OK;
-  if (h->d_tree) { (void)hipFree(h->d_tree); h->d_tree = nullptr; h->d_tree_bytes = 0; }
-  const size_t nn = h->tree.feature.size();
-  const size_t bytes = nn * 8 + nn * 4 * 4 + h->chosen.size() * 4;
+  free_selector_device(h, dtype);
+  const size_t nn = S.tree.feature.size();
+  const size_t bytes = nn * 8 + nn * 4 * 4 + S.chosen.size() * 4;
   std::vector<char> buf(bytes);
   char* p = buf.data();
-  memcpy(p, h->tree.threshold.data(), nn * 8); p += nn * 8;
-  memcpy(p, h->tree.feature.data(), nn * 4); p += nn * 4;
-  memcpy(p, h->tree.left.data(), nn * 4); p += nn * 4;
-  memcpy(p, h->tree.right.data(), nn * 4); p += nn * 4;
-  memcpy(p, h->tree.cls.data(), nn * 4); p += nn * 4;
-  memcpy(p, h->chosen.data(), h->chosen.size() * 4);
-  hipError_t e = hipMalloc(&h->d_tree, bytes);
-  if (e != hipSuccess) { h->d_tree = nullptr; return hip_fail(h, e, "hipMalloc tree"); }
-  e = hipMemcpy(h->d_tree, buf.data(), bytes, hipMemcpyHostToDevice);
+  memcpy(p, S.tree.threshold.data(), nn * 8); p += nn * 8;
+  memcpy(p, S.tree.feature.data(), nn * 4); p += nn * 4;
+  memcpy(p, S.tree.left.data(), nn * 4); p += nn * 4;
+  memcpy(p, S.tree.right.data(), nn * 4); p += nn * 4;
+  memcpy(p, S.tree.cls.data(), nn * 4); p += nn * 4;
+  memcpy(p, S.chosen.data(), S.chosen.size() * 4);
+  hipError_t e = hipMalloc(&S.d_tree, bytes);
+  if (e != hipSuccess) { S.d_tree = nullptr; return hip_fail(h, e, "hipMalloc tree"); }
+  e = hipMemcpy(S.d_tree, buf.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "upload tree");
-  h->d_tree_bytes = bytes;
+  S.d_tree_bytes = bytes;
   return KT_OK;
 }
 
+static int64_t elem_bytes_sel(int dtype) { return dtype == KT_F32 ? 4 : dtype == KT_BF16 ? 2 : 1; }
+
 // Exhaustive selection: time every compiled configuration of the shape's
-// layout on handle-owned scratch operands; the fastest (lowest id on ties) is
-// cached for the shape.
-static kt_status exhaustive_select(Ctx* h, const kt_shape* s, int32_t* out) {
-  const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, h->sel_dtype};
-  auto it = h->exhaustive_cache.find(key);
-  if (it != h->exhaustive_cache.end()) { *out = it->second; return KT_OK; }
+// layout on handle-owned scratch operands (generated in FP32 and converted
+// for BF16 / FP8); the fastest (lowest id on ties) is cached for the shape.
+static kt_status exhaustive_select(Ctx* h, int dtype, const kt_shape* s, int32_t* out) {
+  SelState& S = h->sel[dtype];
+  const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, dtype};
+  auto it = S.exhaustive_cache.find(key);
+  if (it != S.exhaustive_cache.end()) { *out = it->second; return KT_OK; }
   if (!need_device(h)) return KT_EINVAL;
-  const int dtype = h->sel_dtype;
+  const int64_t eb = elem_bytes_sel(dtype);
   const int64_t a_rows = s->transA ? s->K : s->M, a_cols = s->transA ? s->M : s->K;
   const int64_t b_rows = s->transB ? s->N : s->K, b_cols = s->transB ? s->K : s->N;
   const int64_t lda = std::max<int64_t>(a_cols, 1), ldb = std::max<int64_t>(b_cols, 1);
   const int64_t ldc = std::max<int64_t>(s->N, 1);
   const int64_t nA = s->batch * a_rows * lda, nB = s->batch * b_rows * ldb, nC = s->batch * s->M * ldc;
-  const size_t need = (size_t)(nA + nB + nC) * 4 + 1024;
+  auto r256 = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+  const int64_t offB = r256(nA * eb), offC = offB + r256(nB * eb), offS = offC + r256(nC * 4);
+  const int64_t offT = offS + 256;   // FP32 staging for BF16 / FP8 operands
+  const size_t need = (size_t)(offT + (dtype == KT_F32 ? 0 : std::max(nA, nB) * 4) + 256);
   if (h->scratch_bytes < need) {
     if (h->scratch) (void)hipFree(h->scratch);
     h->scratch = nullptr;
@@ -202,12 +220,30 @@ static kt_status exhaustive_select(Ctx* h, const kt_shape* s, int32_t* out) {
     if (e != hipSuccess) return hip_fail(h, e, "hipMalloc exhaustive-selection scratch");
     h->scratch_bytes = need;
   }
-  float* A = (float*)h->scratch;
-  float* B = A + ((nA + 63) & ~63LL);
-  float* C = B + ((nB + 63) & ~63LL);
-  hipError_t e = fill_uniform(A, nA, 1, 0, nullptr);
-  if (e == hipSuccess) e = fill_uniform(B, nB, 2, 0, nullptr);
-  if (e != hipSuccess) return hip_fail(h, e, "fill");
+  char* base = (char*)h->scratch;
+  void* A = base;
+  void* B = base + offB;
+  float* C = (float*)(base + offC);
+  float* scales = (float*)(base + offS);
+  hipError_t e = hipSuccess;
+  if (dtype == KT_F32) {
+    e = fill_uniform((float*)A, nA, 1, 0, nullptr);
+    if (e == hipSuccess) e = fill_uniform((float*)B, nB, 2, 0, nullptr);
+    if (e != hipSuccess) return hip_fail(h, e, "fill");
+  } else {
+    float* stage = (float*)(base + offT);
+    for (int which = 0; which < 2; ++which) {
+      const int64_t n = which == 0 ? nA : nB;
+      void* dst = which == 0 ? A : B;
+      e = fill_uniform(stage, n, 1 + which, 0, nullptr);
+      if (e != hipSuccess) return hip_fail(h, e, "fill");
+      kt_status st = dtype == KT_BF16
+          ? kt_convert_bf16(reinterpret_cast<kt_handle>(h), stage, n, (uint16_t*)dst, nullptr)
+          : kt_quantize_fp8(reinterpret_cast<kt_handle>(h), stage, n, (uint8_t*)dst, scales + which,
+                            scales + 2, 16, nullptr);
+      if (st != KT_OK) return st;
+    }
+  }
   hipEvent_t e0, e1;
   if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(h, e, "event");
   if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(h, e, "event"); }
@@ -218,7 +254,7 @@ static kt_status exhaustive_select(Ctx* h, const kt_shape* s, int32_t* out) {
     if (!find_launcher(h, dtype, id, s->transA, s->transB)) continue;
     auto launch = [&]() {
       return launch_gemm(h, dtype, s, 1.f, A, lda, a_rows * lda, B, ldb, b_rows * ldb, 0.f, C, ldc,
-                         s->M * ldc, nullptr, nullptr, id, nullptr);
+                         s->M * ldc, scales, scales + 1, id, nullptr);
     };
     if ((st = launch()) != KT_OK) break;
     (void)hipEventRecord(e0, nullptr);
@@ -233,28 +269,31 @@ static kt_status exhaustive_select(Ctx* h, const kt_shape* s, int32_t* out) {
   (void)hipEventDestroy(e1);
   if (st != KT_OK) return st;
   if (best < 0) return fail(h, KT_EUNSUPPORTED, "no configuration compiled for this layout");
-  h->exhaustive_cache[key] = best;
+  S.exhaustive_cache[key] = best;
   *out = best;
   return KT_OK;
 }
 
-kt_status select_config(Ctx* h, const kt_shape* s, int32_t* id) {
-  switch (h->sel_kind) {
+kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
+  SelState& S = h->sel[dtype];
+  switch (S.kind) {
     case KT_SEL_DT_A:
     case KT_SEL_DT_B:
     case KT_SEL_DT_C: {
-      const int32_t c = tree_walk(h->tree, *s);
-      *id = h->chosen[c];
+      const int32_t c = tree_walk(S.tree, *s);
+      *id = S.chosen[c];
       return KT_OK;
     }
     case KT_SEL_MLP:
-      return mlp_select_host(h, s, id);
+      return mlp_select_host(h, dtype, s, id);
     case KT_SEL_EXHAUSTIVE:
-      return exhaustive_select(h, s, id);
+      return exhaustive_select(h, dtype, s, id);
     default:
-      return fail(h, KT_ENOTFITTED, "no selector fitted or loaded");
+      return fail(h, KT_ENOTFITTED, "no selector fitted or loaded for this dtype");
   }
 }
+
+static bool bad_dtype(int d) { return d < 0 || d >= NUM_DTYPES; }
 
 }  // namespace kt
 
@@ -262,35 +301,36 @@ using namespace kt;
 
 extern "C" {
 
-kt_status kt_fit_selector(kt_handle hh, kt_selector sel, const kt_shape* shapes,
+kt_status kt_fit_selector(kt_handle hh, kt_dtype dtype, kt_selector sel, const kt_shape* shapes,
                           const int64_t* time_ns, int32_t n, int32_t d, const int32_t* chosen,
                           int32_t k, const kt_mlp_opts* mlp, void* ws, size_t ws_bytes,
                           void* stream) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
+  SelState& S = h->sel[dtype];
   if (sel == KT_SEL_EXHAUSTIVE) {
-    h->sel_kind = KT_SEL_EXHAUSTIVE;
-    h->sel_dtype = KT_F32;
-    h->chosen.clear();
-    h->tree = Tree();
-    h->exhaustive_cache.clear();
+    free_selector_device(h, dtype);
+    S = SelState();
+    S.kind = KT_SEL_EXHAUSTIVE;
     return KT_OK;
   }
   if ((int)sel < 0 || (int)sel > KT_SEL_MLP) return fail(h, KT_EINVAL, "bad selector kind");
   if (n < 1 || d < 1 || !shapes || !time_ns || !chosen || k < 1 || k > d)
     return fail(h, KT_EINVAL, "bad training data");
   for (int32_t j = 0; j < k; ++j) {
-    if (chosen[j] < 0 || chosen[j] >= d || chosen[j] >= (int32_t)h->configs[KT_F32].size())
+    if (chosen[j] < 0 || chosen[j] >= d || chosen[j] >= (int32_t)h->configs[dtype].size())
       return fail(h, KT_EINVAL, "chosen id out of range");
     for (int32_t q = 0; q < j; ++q)
       if (chosen[q] == chosen[j]) return fail(h, KT_EINVAL, "chosen ids must be distinct");
   }
   if (sel == KT_SEL_MLP) {
-    kt_status st = fit_mlp(h, shapes, time_ns, n, d, chosen, k, mlp, ws, ws_bytes, (hipStream_t)stream);
+    kt_status st = fit_mlp(h, dtype, shapes, time_ns, n, d, chosen, k, mlp, ws, ws_bytes,
+                           (hipStream_t)stream);
     if (st != KT_OK) return st;
-    h->sel_kind = KT_SEL_MLP;
-    h->sel_dtype = KT_F32;
-    h->chosen.assign(chosen, chosen + k);
+    S.kind = KT_SEL_MLP;
+    S.tree = Tree();
+    S.exhaustive_cache.clear();
     return KT_OK;
   }
   CartData D;
@@ -316,86 +356,99 @@ kt_status kt_fit_selector(kt_handle hh, kt_selector sel, const kt_shape* shapes,
   std::vector<int32_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   cart_build(D, idx, 0, T);
-  h->tree = std::move(T);
-  h->chosen.assign(chosen, chosen + k);
-  h->sel_kind = sel;
-  h->sel_dtype = KT_F32;
-  return upload_tree(h);
+  free_selector_device(h, dtype);
+  S = SelState();
+  S.tree = std::move(T);
+  S.chosen.assign(chosen, chosen + k);
+  S.kind = sel;
+  return upload_tree(h, dtype);
 }
 
-kt_status kt_select(kt_handle hh, const kt_shape* s, int32_t* config_id) {
+kt_status kt_select(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_t* config_id) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
   if (!s || !config_id) return fail(h, KT_EINVAL, "NULL argument");
   if (s->M < 0 || s->N < 0 || s->K < 0 || s->batch < 0 || (s->transA & ~1) || (s->transB & ~1))
     return fail(h, KT_EINVAL, "bad shape");
-  return select_config(h, s, config_id);
+  return select_config(h, dtype, s, config_id);
 }
 
-kt_status kt_select_batch(kt_handle hh, const kt_shape* d_shapes, int32_t n, int32_t* d_ids,
-                          void* stream) {
+kt_status kt_select_batch(kt_handle hh, kt_dtype dtype, const kt_shape* d_shapes, int32_t n,
+                          int32_t* d_ids, void* stream) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
   if (!need_device(h)) return KT_EINVAL;
   if (n < 0) return fail(h, KT_EINVAL, "n < 0");
   if (n == 0) return KT_OK;
   if (!d_shapes || !d_ids) return fail(h, KT_EINVAL, "NULL argument");
+  SelState& S = h->sel[dtype];
   hipStream_t st = (hipStream_t)stream;
-  if (h->sel_kind >= KT_SEL_DT_A && h->sel_kind <= KT_SEL_DT_C) {
-    if (!h->d_tree) return fail(h, KT_ENOTFITTED, "tree not on the device");
+  if (S.kind >= KT_SEL_DT_A && S.kind <= KT_SEL_DT_C) {
+    if (!S.d_tree) return fail(h, KT_ENOTFITTED, "tree not on the device");
     hipLaunchKernelGGL(select_tree_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d_shapes, n,
-                       (const char*)h->d_tree, (int32_t)h->tree.feature.size(),
-                       (int32_t)h->chosen.size(), d_ids);
+                       (const char*)S.d_tree, (int32_t)S.tree.feature.size(),
+                       (int32_t)S.chosen.size(), d_ids);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "select launch");
     return KT_OK;
   }
-  if (h->sel_kind == KT_SEL_MLP) {
-    return mlp_select_batch(h, d_shapes, n, d_ids, st);
-  }
-  if (h->sel_kind == KT_SEL_EXHAUSTIVE)
+  if (S.kind == KT_SEL_MLP) return mlp_select_batch(h, dtype, d_shapes, n, d_ids, st);
+  if (S.kind == KT_SEL_EXHAUSTIVE)
     return fail(h, KT_EUNSUPPORTED, "exhaustive selection runs per shape on the host (kt_select)");
-  return fail(h, KT_ENOTFITTED, "no selector fitted or loaded");
+  return fail(h, KT_ENOTFITTED, "no selector fitted or loaded for this dtype");
 }
 
-kt_status kt_get_tree(kt_handle hh, int32_t* n_nodes, int32_t* feature, int64_t* threshold,
-                      int32_t* left, int32_t* right, int32_t* cls) {
+kt_status kt_get_tree(kt_handle hh, kt_dtype dtype, int32_t* n_nodes, int32_t* feature,
+                      int64_t* threshold, int32_t* left, int32_t* right, int32_t* cls) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
   if (!n_nodes) return fail(h, KT_EINVAL, "NULL n_nodes");
-  if (h->sel_kind < KT_SEL_DT_A || h->sel_kind > KT_SEL_DT_C) return fail(h, KT_ENOTFITTED, "no tree fitted");
-  const size_t nn = h->tree.feature.size();
+  const SelState& S = h->sel[dtype];
+  if (S.kind < KT_SEL_DT_A || S.kind > KT_SEL_DT_C) return fail(h, KT_ENOTFITTED, "no tree fitted");
+  const size_t nn = S.tree.feature.size();
   *n_nodes = (int32_t)nn;
-  if (feature) memcpy(feature, h->tree.feature.data(), nn * 4);
-  if (threshold) memcpy(threshold, h->tree.threshold.data(), nn * 8);
-  if (left) memcpy(left, h->tree.left.data(), nn * 4);
-  if (right) memcpy(right, h->tree.right.data(), nn * 4);
-  if (cls) memcpy(cls, h->tree.cls.data(), nn * 4);
+  if (feature) memcpy(feature, S.tree.feature.data(), nn * 4);
+  if (threshold) memcpy(threshold, S.tree.threshold.data(), nn * 8);
+  if (left) memcpy(left, S.tree.left.data(), nn * 4);
+  if (right) memcpy(right, S.tree.right.data(), nn * 4);
+  if (cls) memcpy(cls, S.tree.cls.data(), nn * 4);
   return KT_OK;
 }
 
-// Text format:
-//   KTSEL 1
-//   kind <k> dtype <d>
-//   chosen <k> id...
-//   tree <n>          followed by n lines: feature threshold left right cls
-//   mlp <count>       followed by count floats in %a notation
+// Text format (version 2):
+//   KTSEL 2
+//   selectors <count>
+//   then per selector:
+//     dtype <d> kind <k>
+//     chosen <k> id...
+//     tree <n>        followed by n lines: feature threshold left right cls
+//     mlp <count>     followed by count floats in %a notation
 //   end
 kt_status kt_save(kt_handle hh, const char* path) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!path) return fail(h, KT_EINVAL, "NULL path");
-  if (h->sel_kind < 0) return fail(h, KT_ENOTFITTED, "nothing to save");
+  int count = 0;
+  for (int d = 0; d < NUM_DTYPES; ++d) count += h->sel[d].kind >= 0;
+  if (count == 0) return fail(h, KT_ENOTFITTED, "nothing to save");
   FILE* f = fopen(path, "w");
   if (!f) return fail(h, KT_EIO, std::string("cannot write ") + path);
-  fprintf(f, "KTSEL 1\nkind %d dtype %d\nchosen %zu", h->sel_kind, h->sel_dtype, h->chosen.size());
-  for (int32_t c : h->chosen) fprintf(f, " %d", c);
-  fprintf(f, "\ntree %zu\n", h->tree.feature.size());
-  for (size_t i = 0; i < h->tree.feature.size(); ++i)
-    fprintf(f, "%d %lld %d %d %d\n", h->tree.feature[i], (long long)h->tree.threshold[i],
-            h->tree.left[i], h->tree.right[i], h->tree.cls[i]);
-  fprintf(f, "mlp %zu\n", h->mlp.params.size());
-  for (float v : h->mlp.params) fprintf(f, "%a\n", (double)v);
+  fprintf(f, "KTSEL 2\nselectors %d\n", count);
+  for (int d = 0; d < NUM_DTYPES; ++d) {
+    const SelState& S = h->sel[d];
+    if (S.kind < 0) continue;
+    fprintf(f, "dtype %d kind %d\nchosen %zu", d, S.kind, S.chosen.size());
+    for (int32_t c : S.chosen) fprintf(f, " %d", c);
+    fprintf(f, "\ntree %zu\n", S.tree.feature.size());
+    for (size_t i = 0; i < S.tree.feature.size(); ++i)
+      fprintf(f, "%d %lld %d %d %d\n", S.tree.feature[i], (long long)S.tree.threshold[i],
+              S.tree.left[i], S.tree.right[i], S.tree.cls[i]);
+    fprintf(f, "mlp %zu\n", S.mlp.params.size());
+    for (float v : S.mlp.params) fprintf(f, "%a\n", (double)v);
+  }
   fprintf(f, "end\n");
   const bool ok = fflush(f) == 0 && !ferror(f);
   fclose(f);
@@ -411,56 +464,65 @@ kt_status kt_load(kt_handle hh, const char* path) {
   if (!in) return fail(h, KT_EIO, std::string("cannot read ") + path);
   auto bad = [&](const char* why) { return fail(h, KT_EIO, std::string("malformed selector file: ") + why); };
   std::string tag;
-  int ver = 0, kind = -1, dtype = -1;
-  if (!(in >> tag >> ver) || tag != "KTSEL" || ver != 1) return bad("header");
-  if (!(in >> tag >> kind) || tag != "kind" || kind < KT_SEL_DT_A || kind > KT_SEL_EXHAUSTIVE) return bad("kind");
-  if (!(in >> tag >> dtype) || tag != "dtype" || dtype != KT_F32) return bad("dtype");
-  size_t k = 0;
-  if (!(in >> tag >> k) || tag != "chosen" || k > 4096) return bad("chosen");
-  std::vector<int32_t> chosen(k);
-  for (size_t j = 0; j < k; ++j)
-    if (!(in >> chosen[j]) || chosen[j] < 0 || chosen[j] >= (int32_t)h->configs[KT_F32].size()) return bad("chosen id");
-  size_t nn = 0;
-  if (!(in >> tag >> nn) || tag != "tree" || nn > (1u << 24)) return bad("tree");
-  Tree T;
-  T.feature.resize(nn); T.threshold.resize(nn); T.left.resize(nn); T.right.resize(nn); T.cls.resize(nn);
-  for (size_t i = 0; i < nn; ++i) {
-    long long thr;
-    if (!(in >> T.feature[i] >> thr >> T.left[i] >> T.right[i] >> T.cls[i])) return bad("tree node");
-    T.threshold[i] = thr;
-    if (T.feature[i] < -1 || T.feature[i] > 5) return bad("feature");
-    if (T.feature[i] >= 0 && (T.left[i] <= (int32_t)i || T.right[i] <= (int32_t)i ||
-                              T.left[i] >= (int32_t)nn || T.right[i] >= (int32_t)nn))
-      return bad("child index");
-    if (T.cls[i] < 0 || T.cls[i] >= (int32_t)std::max<size_t>(k, 1)) return bad("class");
-  }
-  size_t np = 0;
-  if (!(in >> tag >> np) || tag != "mlp" || np > (1u << 24)) return bad("mlp");
-  std::vector<float> params(np);
-  for (size_t i = 0; i < np; ++i) {
-    std::string tok;
-    if (!(in >> tok)) return bad("mlp value");
-    char* endp = nullptr;
-    const double v = strtod(tok.c_str(), &endp);
-    if (!endp || *endp) return bad("mlp value");
-    params[i] = (float)v;
+  int ver = 0, count = 0;
+  if (!(in >> tag >> ver) || tag != "KTSEL" || ver != 2) return bad("header");
+  if (!(in >> tag >> count) || tag != "selectors" || count < 1 || count > NUM_DTYPES) return bad("selector count");
+  struct Loaded { int dtype, kind; std::vector<int32_t> chosen; Tree tree; std::vector<float> params; };
+  std::vector<Loaded> all;
+  for (int q = 0; q < count; ++q) {
+    Loaded L;
+    if (!(in >> tag >> L.dtype) || tag != "dtype" || bad_dtype(L.dtype)) return bad("dtype");
+    for (const Loaded& o : all) if (o.dtype == L.dtype) return bad("duplicate dtype");
+    if (!(in >> tag >> L.kind) || tag != "kind" || L.kind < KT_SEL_DT_A || L.kind > KT_SEL_EXHAUSTIVE) return bad("kind");
+    size_t k = 0;
+    if (!(in >> tag >> k) || tag != "chosen" || k > 4096) return bad("chosen");
+    L.chosen.resize(k);
+    for (size_t j = 0; j < k; ++j)
+      if (!(in >> L.chosen[j]) || L.chosen[j] < 0 || L.chosen[j] >= (int32_t)h->configs[L.dtype].size())
+        return bad("chosen id");
+    size_t nn = 0;
+    if (!(in >> tag >> nn) || tag != "tree" || nn > (1u << 24)) return bad("tree");
+    Tree& T = L.tree;
+    T.feature.resize(nn); T.threshold.resize(nn); T.left.resize(nn); T.right.resize(nn); T.cls.resize(nn);
+    for (size_t i = 0; i < nn; ++i) {
+      long long thr;
+      if (!(in >> T.feature[i] >> thr >> T.left[i] >> T.right[i] >> T.cls[i])) return bad("tree node");
+      T.threshold[i] = thr;
+      if (T.feature[i] < -1 || T.feature[i] > 5) return bad("feature");
+      if (T.feature[i] >= 0 && (T.left[i] <= (int32_t)i || T.right[i] <= (int32_t)i ||
+                                T.left[i] >= (int32_t)nn || T.right[i] >= (int32_t)nn))
+        return bad("child index");
+      if (T.cls[i] < 0 || T.cls[i] >= (int32_t)std::max<size_t>(k, 1)) return bad("class");
+    }
+    size_t np = 0;
+    if (!(in >> tag >> np) || tag != "mlp" || np > (1u << 24)) return bad("mlp");
+    L.params.resize(np);
+    for (size_t i = 0; i < np; ++i) {
+      std::string tok;
+      if (!(in >> tok)) return bad("mlp value");
+      char* endp = nullptr;
+      const double v = strtod(tok.c_str(), &endp);
+      if (!endp || *endp) return bad("mlp value");
+      L.params[i] = (float)v;
+    }
+    if (L.kind <= KT_SEL_DT_C && (nn == 0 || k == 0)) return bad("tree selector without nodes");
+    if (L.kind == KT_SEL_MLP && np != (size_t)64 * 6 + 64 + 64 * 64 + 64 + k * 64 + k) return bad("mlp size");
+    all.push_back(std::move(L));
   }
   if (!(in >> tag) || tag != "end") return bad("end");
-  if (kind <= KT_SEL_DT_C && (nn == 0 || k == 0)) return bad("tree selector without nodes");
-  if (kind == KT_SEL_MLP) {
-    const size_t want = (size_t)64 * 6 + 64 + 64 * 64 + 64 + k * 64 + k;
-    if (np != want) return bad("mlp size");
-  }
-  h->sel_kind = kind;
-  h->sel_dtype = dtype;
-  h->chosen = chosen;
-  h->tree = std::move(T);
-  h->mlp.k = (int32_t)k;
-  h->mlp.params = std::move(params);
-  h->exhaustive_cache.clear();
-  if (kind <= KT_SEL_DT_C) return upload_tree(h);
-  if (kind == KT_SEL_MLP) {
-    return mlp_upload(h);
+  for (Loaded& L : all) {
+    free_selector_device(h, L.dtype);
+    SelState& S = h->sel[L.dtype];
+    S = SelState();
+    S.kind = L.kind;
+    S.chosen = L.chosen;
+    S.tree = std::move(L.tree);
+    S.mlp.k = (int32_t)L.chosen.size();
+    S.mlp.params = std::move(L.params);
+    kt_status st = KT_OK;
+    if (S.kind <= KT_SEL_DT_C) st = upload_tree(h, L.dtype);
+    else if (S.kind == KT_SEL_MLP) st = mlp_upload(h, L.dtype);
+    if (st != KT_OK) return st;
   }
   return KT_OK;
 }

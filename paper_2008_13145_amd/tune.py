@@ -21,6 +21,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "data", "sweep_f32_mi355x.npz")
+DTYPE_NAMES = {"f32": 0, "bf16": 1, "fp8": 2}
+
+
+def table_path(dtype_name: str) -> str:
+    return os.path.join(HERE, "data", f"sweep_{dtype_name}_mi355x.npz")
 DEPLOY_SPEC = os.path.join(HERE, "data", "deploy_f32.json")
 DEPLOY_LIB = os.path.join(HERE, "libkt_deploy.so")
 
@@ -41,7 +46,7 @@ def save_table(path, time_ns, problems, configs, meta):
 
 
 def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
-              cut_factor=8.0, warmup=0, limit=None, log=print):
+              cut_factor=8.0, warmup=0, limit=None, log=print, dtype=0):
     import torch
 
     import synth
@@ -50,7 +55,7 @@ def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
     problems = synth.sweep_problems()
     if limit:
         problems = problems[:limit]
-    configs = h.configs()
+    configs = h.configs(dtype)
     if os.path.exists(out):
         T, P, C, meta = load_table(out)
         if P.tolist() != [list(p) for p in problems] or C.tolist() != [list(c) for c in configs]:
@@ -61,13 +66,14 @@ def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
         meta = dict(device=props.name, arch=getattr(props, "gcnArchName", ""),
                     opts=dict(target_ms=target_ms, min_reps=min_reps, max_reps=max_reps,
                               cut_factor=cut_factor, warmup=warmup),
-                    seed=synth.SEED, started=time.time(), seconds=0.0)
-    ws_bytes = Handle.sweep_workspace_bytes(problems)
+                    seed=synth.SEED, started=time.time(), seconds=0.0, dtype=dtype)
+    ws_bytes = Handle.sweep_workspace_bytes(problems, dtype)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     # Load every kernel once on a tiny problem, so that no row pays for code
     # object loading and the first timed launch of a pair is representative.
     tiny = [(8, 8, 8, 1, ta, tb) for (ta, tb) in synth.LAYOUTS]
-    h.sweep(tiny, ws, ws_bytes, warmup=0, target_ms=0.0, min_reps=1, max_reps=1, cut_factor=0.0)
+    h.sweep(tiny, ws, ws_bytes, warmup=0, target_ms=0.0, min_reps=1, max_reps=1, cut_factor=0.0,
+            dtype=dtype)
     t0 = time.time()
     last_save = time.time()
     todo = [i for i in range(len(problems)) if (T[i] < 0).any()]
@@ -79,7 +85,7 @@ def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
         sub = T[i:i + 1].copy()
         ts = time.time()
         h.sweep([problems[i]], ws, ws_bytes, time_ns=sub, warmup=warmup, target_ms=target_ms,
-                min_reps=min_reps, max_reps=max_reps, cut_factor=cut_factor)
+                min_reps=min_reps, max_reps=max_reps, cut_factor=cut_factor, dtype=dtype)
         T[i] = sub[0]
         meta["seconds"] = meta.get("seconds", 0.0) + (time.time() - ts)
         if time.time() - last_save > 20 or n_done == len(todo) - 1:
@@ -100,7 +106,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("sweep")
-    s.add_argument("--out", default=DEFAULT_TABLE)
+    s.add_argument("--dtype", default="f32", choices=sorted(DTYPE_NAMES))
+    s.add_argument("--out", default=None)
     s.add_argument("--budget-s", type=float, default=900.0)
     s.add_argument("--limit", type=int, default=None)
     d = sub.add_parser("deploy")
@@ -111,7 +118,7 @@ def main(argv=None):
     d.add_argument("--no-build", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
-        run_sweep(a.out, a.budget_s, limit=a.limit)
+        run_sweep(a.out or table_path(a.dtype), a.budget_s, limit=a.limit, dtype=DTYPE_NAMES[a.dtype])
     elif a.cmd == "deploy":
         # choose the k kernels by GPU k-means over the training problems of the
         # measured table, record them, and build the library with only those

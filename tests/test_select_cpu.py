@@ -65,8 +65,8 @@ def test_save_load_roundtrip_and_corruption(kt, tmp_path):
     for s in shapes[::5]:
         assert h2.select(*s) == h.select(*s)
     txt = open(p).read()
-    for bad in (txt.replace("KTSEL 1", "KTSEL 9"), txt[: len(txt) // 2], txt.replace("tree", "tre"),
-                txt.replace("chosen 3 1 2 5", "chosen 3 1 2 999")):
+    for bad in (txt.replace("KTSEL 2", "KTSEL 9"), txt[: len(txt) // 2], txt.replace("tree", "tre"),
+                txt.replace("chosen 3 1 2 5", "chosen 3 1 2 999"), txt.replace("dtype 0", "dtype 7")):
         q = str(tmp_path / "bad.txt")
         open(q, "w").write(bad)
         h3 = kt.Handle(-1)
@@ -93,3 +93,33 @@ def test_bad_fit_arguments(kt):
         with pytest.raises(kt.KtError) as e:
             h.fit_selector(0, shapes, T, chosen)
         assert e.value.status == -1
+
+
+def test_selectors_are_per_dtype(kt, tmp_path):
+    """Each dtype has its own selector: fitting one leaves the others alone,
+    and the file keeps all of them."""
+    rng = np.random.default_rng(9)
+    shapes, T = _table(rng, 50, 30, 123)
+    h = kt.Handle(-1)
+    h.fit_selector(0, shapes, T, [1, 2, 3], dtype=kt.F32)
+    with pytest.raises(kt.KtError) as e:
+        h.select(64, 64, 64, dtype=kt.BF16)
+    assert e.value.status == -4
+    T2 = T[:, ::-1].copy()
+    h.fit_selector(2, shapes, T2, [10, 20], dtype=kt.BF16)
+    assert all(h.select(*s, dtype=kt.F32) in (1, 2, 3) for s in shapes[::3])
+    assert all(h.select(*s, dtype=kt.BF16) in (10, 20) for s in shapes[::3])
+    ref = cart.fit(np.array(shapes), cart.labels_from_times(T2, [10, 20]), 2, 3, 4)
+    assert h.get_tree(dtype=kt.BF16) == {key: [int(v) for v in ref[key]] for key in ref}
+    p = str(tmp_path / "two.txt")
+    h.save(p)
+    h2 = kt.Handle(-1)
+    h2.load(p)
+    for s in shapes[::4]:
+        assert h2.select(*s, dtype=kt.F32) == h.select(*s, dtype=kt.F32)
+        assert h2.select(*s, dtype=kt.BF16) == h.select(*s, dtype=kt.BF16)
+    with pytest.raises(kt.KtError):
+        h2.select(64, 64, 64, dtype=kt.FP8E4M3)
+    with pytest.raises(kt.KtError) as e:
+        h.fit_selector(0, shapes, T, [59], dtype=kt.BF16)     # BF16 has 59 configurations
+    assert e.value.status == -1
