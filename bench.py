@@ -94,6 +94,96 @@ def measured_traffic(kernel_name):
     return None
 
 
+def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k, steps, stream):
+    """BF16 / FP8 paths on the same 1200 problems: their own sweep tables,
+    k-means pruning and decision tree B on the training shapes, a live pass of
+    the deployed path, and the speedup over the FP32 exhaustive best."""
+    out = {}
+    train, test = synth.train_test_split()
+    tr_rows, te_rows = synth.rows_of_shapes(train), synth.rows_of_shapes(test)
+    t32 = T32.min(axis=1).astype(np.float64)
+    n = pool.numel()
+    for name, dt, eb in (("bf16", kt.BF16, 2), ("fp8", kt.FP8E4M3, 1)):
+        path = tune.table_path(name)
+        if not os.path.exists(path):
+            continue
+        TL, PL, CL, metaL = tune.load_table(path)
+        if not (TL >= 0).all() or [tuple(int(v) for v in p) for p in PL] != problems:
+            continue
+        tl = TL.min(axis=1).astype(np.float64)
+        ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), TL.shape[1], k, 10)
+        pws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        chosen = h.prune(TL[tr_rows], k, norm=kt.NORM_RELATIVE, seed=synth.SEED, n_init=10,
+                         max_iter=300, workspace=pws, ws_bytes=ws_bytes, stream=stream)["chosen"]
+        h.fit_selector(kt.SEL_DT_B, [problems[r] for r in tr_rows], TL[tr_rows], chosen, dtype=dt)
+        picks = [h.select(*p, dtype=dt) for p in problems]
+        ratio = tl / TL[np.arange(len(problems)), picks]
+        ceil = tl[te_rows] / np.array([TL[r, chosen].min() for r in te_rows])
+        # operands in the low-precision format, converted on the GPU from the FP32 pool
+        lp = torch.empty(n * eb + 256, dtype=torch.uint8, device="cuda")
+        scales = torch.empty(4, dtype=torch.float32, device="cuda")
+        if dt == kt.BF16:
+            h.convert_bf16(pool, n, lp, stream=stream)
+        else:
+            h.quantize_fp8(pool, n, lp, scales, scales[2:], 8, stream=stream)
+        base32, baselp = pool.data_ptr(), lp.data_ptr()
+
+        def step():
+            for pl in plans:
+                h.gemm_raw(dt, pl[0], 1.0, baselp + (pl[1] - base32) // 4 * eb, pl[2], pl[3],
+                           baselp + (pl[4] - base32) // 4 * eb, pl[5], pl[6], 0.0, pl[7], pl[8],
+                           pl[9], scaleA=scales.data_ptr(), scaleB=scales.data_ptr(),
+                           config_id=-1, stream=stream)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[name] = {
+            "live_tflops": round(float(flops.sum()) / (ms * 1e-3) / 1e12, 2),
+            "ms_per_step": round(ms, 3),
+            "exhaustive_best_tflops": round(float(flops.sum()) / (tl.sum() * 1e-9) / 1e12, 2),
+            "speedup_vs_f32_best_geomean": round(_geomean(t32 / tl), 3),
+            "speedup_vs_f32_best_time_weighted": round(float(t32.sum() / tl.sum()), 3),
+            "pct_of_exhaustive_all_rows_table": round(100 * _geomean(ratio), 2),
+            "dt_b_pct_of_optimal_test": round(100 * _geomean(ratio[te_rows]), 2),
+            "kmeans_ceiling_test": round(100 * _geomean(ceil), 2),
+            "chosen": [list(h.get_config(c, dt)) for c in chosen],
+            "accuracy_bound_rel_frobenius": 1e-2 if dt == kt.BF16 else 4e-2,
+        }
+        del lp
+    return out
+
+
+def conv_section(kt, h, tune, problems_conv_path, sel_kinds, fit_args):
+    """Held-out generalization: the GEMMs of a VGG16-style conv stack (im2col
+    and Winograd lowerings, never seen in training) through the selectors
+    fitted on the sweep set, judged against their own exhaustive sweep."""
+    if not os.path.exists(problems_conv_path):
+        return None
+    TC, PC, CC, metaC = tune.load_table(problems_conv_path)
+    if not (TC >= 0).all():
+        return None
+    probs = [tuple(int(v) for v in p) for p in PC]
+    F = np.array([2.0 * p[0] * p[1] * p[2] * p[3] for p in probs])
+    tb = TC.min(axis=1).astype(np.float64)
+    out = {"problems": len(probs), "gflop": round(float(F.sum()) / 1e9, 1),
+           "exhaustive_best_tflops": round(float(F.sum()) / (tb.sum() * 1e-9) / 1e12, 2)}
+    tr_shapes, T_tr, chosen, mws, mws_bytes, stream = fit_args
+    for kind in sel_kinds:
+        h.fit_selector(kind, tr_shapes, T_tr, chosen, mlp_steps=3000, mlp_graph_steps=25,
+                       workspace=mws, ws_bytes=mws_bytes, stream=stream)
+        picks = [h.select(*p) for p in probs]
+        ts = TC[np.arange(len(probs)), picks].astype(np.float64)
+        out[SEL_NAMES[kind]] = {"pct_of_optimal_geomean": round(100 * _geomean(tb / ts), 2),
+                                "selected_tflops_table": round(float(F.sum()) / (ts.sum() * 1e-9) / 1e12, 2)}
+    ceil = np.array([TC[i, chosen].min() for i in range(len(probs))], dtype=np.float64)
+    out["kmeans_ceiling_pct"] = round(100 * _geomean(tb / ceil), 2)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +194,7 @@ def main(argv=None):
     ap.add_argument("--table", default=None)
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lowp", action="store_true", help="skip the BF16/FP8 sections")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
@@ -174,6 +265,8 @@ def main(argv=None):
         fit_ms[SEL_NAMES[kind]] = (time.perf_counter() - t0) * 1e3
         picks = [h.select(*problems[r]) for r in te_rows]
         evals[SEL_NAMES[kind]] = _geomean(ratios(te_rows, picks))
+    conv = conv_section(kt, h, tune, tune.table_path("f32", "conv"), (0, 1, 2, 3),
+                        (tr_shapes, T[tr_rows], chosen, mws, mws_bytes, stream))
     sel_kind = {v: kk for kk, v in SEL_NAMES.items()}[a.selector]
     h.fit_selector(sel_kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
                    workspace=mws, ws_bytes=mws_bytes, stream=stream)
@@ -292,6 +385,13 @@ def main(argv=None):
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
+    if conv:
+        out["conv_heldout"] = conv
+    if not a.no_lowp:
+        lp = lowp_section(kt, h, torch, tune, synth, problems, T, pool, plans, flops, k, 3, stream)
+        if lp:
+            out["lowp"] = lp
+            _log(f"bench: low precision {json.dumps(lp)}")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problems, a.cpu_budget_s)
     h.close()

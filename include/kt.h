@@ -337,7 +337,7 @@ kt_status kt_mlp_features(kt_handle h, const kt_shape* d_shapes, int32_t n, floa
  * packed like the parameters) and the sum of squared errors d_loss[0]
  * (optional; the loss is that over n*k).  Gradients need d_Y[n][k] and a
  * workspace of nblocks*(n_params*4) + nblocks*4 bytes (256-aligned parts),
- * nblocks = ceil(n / 64); kt_mlp_workspace_bytes is always enough. */
+ * nblocks = ceil(n / 32); kt_mlp_workspace_bytes is always enough. */
 kt_status kt_mlp_forward_backward(kt_handle h, const float* d_params, const float* d_X,
                                   const float* d_Y, int32_t n, int32_t k, float* d_pred,
                                   float* d_grad, float* d_loss, void* workspace, size_t ws_bytes,

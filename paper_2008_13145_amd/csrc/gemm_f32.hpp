@@ -195,6 +195,8 @@ gemm_f32_kernel(GemmArgs args) {
     if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
     const float* as = As + buf * Cfg::A_STAGE;
     const float* bs = Bs + buf * Cfg::B_STAGE;
+    // All MFMA operands of the stage are read from LDS first, then the MFMAs
+    // issue back to back (they chain on the accumulator).
     if constexpr (T == 1) {
       // 16 blocks of 4x4x1: block b = lane/4 -> output block ob = b%4 of the
       // 2x2 grid of 4x4 blocks, K offset ks = b/4.
@@ -202,37 +204,43 @@ gemm_f32_kernel(GemmArgs args) {
       const int ob = b & 3, ks = b >> 2;
       const int ar = wm0 + 4 * (ob >> 1) + i;
       const int bc = wn0 + 4 * (ob & 1) + i;
-      f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+      float af[BK / 4], bf[BK / 4];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        const float a = as[(kk + ks) * Cfg::LDA_S + ar];
-        const float bv = bs[(kk + ks) * Cfg::LDB_S + bc];
-        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bv, c, 0, 0, 0);
+        af[kk / 4] = as[(kk + ks) * Cfg::LDA_S + ar];
+        bf[kk / 4] = bs[(kk + ks) * Cfg::LDB_S + bc];
       }
+      f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+      for (int q = 0; q < BK / 4; ++q) c = __builtin_amdgcn_mfma_f32_4x4x1f32(af[q], bf[q], c, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[r] = c[r];
     } else if constexpr (T == 2) {
       const int r16 = lane & 15, kq = lane >> 4;
-      f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+      float af[BK / 4], bf[BK / 4];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        const float a = as[(kk + kq) * Cfg::LDA_S + wm0 + r16];
-        const float bv = bs[(kk + kq) * Cfg::LDB_S + wn0 + r16];
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, c, 0, 0, 0);
+        af[kk / 4] = as[(kk + kq) * Cfg::LDA_S + wm0 + r16];
+        bf[kk / 4] = bs[(kk + kq) * Cfg::LDB_S + wn0 + r16];
       }
+      f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+#pragma unroll
+      for (int q = 0; q < BK / 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q], bf[q], c, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[r] = c[r];
     } else if constexpr (T == 4) {
       const int r32 = lane & 31, kh = lane >> 5;
+      float af[BK / 2], bf[BK / 2];
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        af[kk / 2] = as[(kk + kh) * Cfg::LDA_S + wm0 + r32];
+        bf[kk / 2] = bs[(kk + kh) * Cfg::LDB_S + wn0 + r32];
+      }
       f32x16 c;
 #pragma unroll
       for (int r = 0; r < 16; ++r) c[r] = acc[r];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 2) {
-        const float a = as[(kk + kh) * Cfg::LDA_S + wm0 + r32];
-        const float bv = bs[(kk + kh) * Cfg::LDB_S + wn0 + r32];
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, c, 0, 0, 0);
-      }
+      for (int q = 0; q < BK / 2; ++q) c = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bf[q], c, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = c[r];
     } else {
@@ -242,16 +250,25 @@ gemm_f32_kernel(GemmArgs args) {
       for (int r = 0; r < 16; ++r) {
         c00[r] = acc[r]; c01[r] = acc[16 + r]; c10[r] = acc[32 + r]; c11[r] = acc[48 + r];
       }
+      // T = 8 holds 64 accumulators; operands are read a half stage at a time
+      constexpr int HALF = BK / 2 > 16 ? 16 : BK / 2;
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 2) {
-        const float* ar = as + (kk + kh) * Cfg::LDA_S + wm0 + r32;
-        const float* br = bs + (kk + kh) * Cfg::LDB_S + wn0 + r32;
-        const float a0 = ar[0], a1 = ar[32];
-        const float b0 = br[0], b1 = br[32];
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, c01, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, c10, 0, 0, 0);
-        c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, c11, 0, 0, 0);
+      for (int k0 = 0; k0 < BK; k0 += 2 * HALF) {
+        float a0[HALF], a1[HALF], b0[HALF], b1[HALF];
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) {
+          const float* ar = as + (k0 + 2 * q + kh) * Cfg::LDA_S + wm0 + r32;
+          const float* br = bs + (k0 + 2 * q + kh) * Cfg::LDB_S + wn0 + r32;
+          a0[q] = ar[0]; a1[q] = ar[32];
+          b0[q] = br[0]; b1[q] = br[32];
+        }
+#pragma unroll
+        for (int q = 0; q < HALF; ++q) {
+          c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[q], b0[q], c00, 0, 0, 0);
+          c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[q], b1[q], c01, 0, 0, 0);
+          c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[q], b0[q], c10, 0, 0, 0);
+          c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[q], b1[q], c11, 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {

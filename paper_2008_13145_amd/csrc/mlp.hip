@@ -9,7 +9,7 @@
 // Targets: relative performance (Q16 / 65535) of the chosen kernels.  Loss:
 // mean squared error over rows x k.  Full-batch Adam with bias correction.
 //
-// GPU layout: one work-group per 64-row block runs forward and backward for
+// GPU layout: one work-group per 32-row block runs forward and backward for
 // its rows entirely in LDS and writes partial gradients; a second kernel sums
 // the partials in block order (deterministic) and applies Adam.  A training
 // run replays a captured hipGraph of several steps.
@@ -26,7 +26,7 @@ namespace kt {
 
 static constexpr int MLP_IN = 6;
 static constexpr int MLP_H = 64;
-static constexpr int MLP_ROWS = 64;      // rows per work-group
+static constexpr int MLP_ROWS = 32;      // rows per work-group
 static constexpr int MLP_THREADS = 256;
 static constexpr int MLP_MAX_K = 64;
 
@@ -68,40 +68,53 @@ __global__ void mlp_targets_kernel(const uint16_t* __restrict__ Xq, int n, int d
   Y[e] = (float)Xq[i * d + chosen[j]] * (1.0f / 65535.0f);
 }
 
-// Forward and backward of one 64-row block.  Writes the block's partial
-// gradient (same layout as the parameters) and partial sum of squared errors;
-// optionally the predictions.  step: block 0 increments the Adam step counter.
+// Forward and backward of one block of MLP_ROWS rows.  Writes the block's
+// partial gradient (same layout as the parameters) and partial sum of
+// squared errors; optionally the predictions.  step: block 0 increments the
+// Adam step counter.  Weight rows sit in LDS with an odd stride (7, 65) so
+// that the 64 lanes of a wave, which read one column of 64 different rows,
+// hit 64 different banks.
+static constexpr int W1S = MLP_IN + 1;     // LDS row strides of W1, W2, W3
+static constexpr int W2S = MLP_H + 1;
+static constexpr int W3S = MLP_H + 1;
+
 __global__ void __launch_bounds__(MLP_THREADS)
 mlp_fwdbwd_kernel(const float* __restrict__ P, const float* __restrict__ X, const float* __restrict__ Y,
                   int n, int k, float* __restrict__ part, float* __restrict__ part_loss,
                   float* __restrict__ pred, int* __restrict__ step) {
   extern __shared__ float sm[];
   const MlpLayout L(k);
-  float* w = sm;                                   // parameters [L.total]
-  float* xs = w + ((L.total + 3) & ~3);            // [64][6]
-  float* z1 = xs + MLP_ROWS * MLP_IN;              // [64][64]  z1, later dz1
-  float* z2 = z1 + MLP_ROWS * MLP_H;               // [64][64]  z2, later dz2
-  float* yy = z2 + MLP_ROWS * MLP_H;               // [64][k]   y, later dy
-  float* dh = yy + MLP_ROWS * MLP_MAX_K;           // [64][64]  dh2, later dh1
+  float* W1 = sm;                                  // [64][W1S]
+  float* W2 = W1 + MLP_H * W1S;                    // [64][W2S]
+  float* W3 = W2 + MLP_H * W2S;                    // [k][W3S]
+  float* b1 = W3 + MLP_MAX_K * W3S;                // [64]
+  float* b2 = b1 + MLP_H;                          // [64]
+  float* b3 = b2 + MLP_H;                          // [k]
+  float* xs = b3 + MLP_MAX_K;                      // [ROWS][6]
+  float* z1 = xs + MLP_ROWS * MLP_IN;              // [ROWS][64]  z1
+  float* z2 = z1 + MLP_ROWS * MLP_H;               // [ROWS][64]  z2, later dz1
+  float* yy = z2 + MLP_ROWS * MLP_H;               // [ROWS][MAX_K] dy
+  float* dh = yy + MLP_ROWS * MLP_MAX_K;           // [ROWS][64]  dz2
   __shared__ float red[MLP_THREADS];
   const int tid = threadIdx.x;
   const int r0 = blockIdx.x * MLP_ROWS;
   const int rows = min(MLP_ROWS, n - r0);
   if (blockIdx.x == 0 && tid == 0 && step) *step += 1;
-  for (int e = tid; e < L.total; e += MLP_THREADS) w[e] = P[e];
+  for (int e = tid; e < MLP_H * MLP_IN; e += MLP_THREADS) W1[(e / MLP_IN) * W1S + e % MLP_IN] = P[L.oW1 + e];
+  for (int e = tid; e < MLP_H * MLP_H; e += MLP_THREADS) W2[(e / MLP_H) * W2S + e % MLP_H] = P[L.oW2 + e];
+  for (int e = tid; e < k * MLP_H; e += MLP_THREADS) W3[(e / MLP_H) * W3S + e % MLP_H] = P[L.oW3 + e];
+  for (int e = tid; e < MLP_H; e += MLP_THREADS) { b1[e] = P[L.ob1 + e]; b2[e] = P[L.ob2 + e]; }
+  for (int e = tid; e < k; e += MLP_THREADS) b3[e] = P[L.ob3 + e];
   for (int e = tid; e < MLP_ROWS * MLP_IN; e += MLP_THREADS) {
     const int r = e / MLP_IN;
     xs[e] = r < rows ? X[(int64_t)(r0 + r) * MLP_IN + e % MLP_IN] : 0.f;
   }
   __syncthreads();
-  const float* W1 = w + L.oW1; const float* b1 = w + L.ob1;
-  const float* W2 = w + L.oW2; const float* b2 = w + L.ob2;
-  const float* W3 = w + L.oW3; const float* b3 = w + L.ob3;
-  // z1 = x W1^T + b1
+  // z1 = x W1^T + b1          (lane -> output unit o)
   for (int e = tid; e < MLP_ROWS * MLP_H; e += MLP_THREADS) {
     const int r = e / MLP_H, o = e % MLP_H;
     float s = b1[o];
-    for (int i = 0; i < MLP_IN; ++i) s = fmaf(xs[r * MLP_IN + i], W1[o * MLP_IN + i], s);
+    for (int i = 0; i < MLP_IN; ++i) s = fmaf(xs[r * MLP_IN + i], W1[o * W1S + i], s);
     z1[e] = s;
   }
   __syncthreads();
@@ -109,7 +122,7 @@ mlp_fwdbwd_kernel(const float* __restrict__ P, const float* __restrict__ X, cons
   for (int e = tid; e < MLP_ROWS * MLP_H; e += MLP_THREADS) {
     const int r = e / MLP_H, o = e % MLP_H;
     float s = b2[o];
-    for (int i = 0; i < MLP_H; ++i) s = fmaf(fmaxf(z1[r * MLP_H + i], 0.f), W2[o * MLP_H + i], s);
+    for (int i = 0; i < MLP_H; ++i) s = fmaf(fmaxf(z1[r * MLP_H + i], 0.f), W2[o * W2S + i], s);
     z2[e] = s;
   }
   __syncthreads();
@@ -119,7 +132,7 @@ mlp_fwdbwd_kernel(const float* __restrict__ P, const float* __restrict__ X, cons
   for (int e = tid; e < MLP_ROWS * k; e += MLP_THREADS) {
     const int r = e / k, o = e % k;
     float s = b3[o];
-    for (int i = 0; i < MLP_H; ++i) s = fmaf(fmaxf(z2[r * MLP_H + i], 0.f), W3[o * MLP_H + i], s);
+    for (int i = 0; i < MLP_H; ++i) s = fmaf(fmaxf(z2[r * MLP_H + i], 0.f), W3[o * W3S + i], s);
     float dy = 0.f;
     if (r < rows) {
       if (pred) pred[(int64_t)(r0 + r) * k + o] = s;
@@ -140,7 +153,7 @@ mlp_fwdbwd_kernel(const float* __restrict__ P, const float* __restrict__ X, cons
   if (!part) return;   // inference only (uniform across the block)
   if (tid == 0) part_loss[blockIdx.x] = red[0];
   float* g = part + (int64_t)blockIdx.x * L.total;
-  // dW3[o][i] = sum_r dy[r][o] relu(z2[r][i]);  db3[o] = sum_r dy[r][o]
+  // dW3[o][i] = sum_r dy[r][o] relu(z2[r][i]);  db3[o] = sum_r dy[r][o]   (lane -> i)
   for (int e = tid; e < k * MLP_H; e += MLP_THREADS) {
     const int o = e / MLP_H, i = e % MLP_H;
     float s = 0.f;
@@ -152,15 +165,15 @@ mlp_fwdbwd_kernel(const float* __restrict__ P, const float* __restrict__ X, cons
     for (int r = 0; r < MLP_ROWS; ++r) s += yy[r * MLP_MAX_K + o];
     g[L.ob3 + o] = s;
   }
-  // dh2 = dy W3 ; dz2 = dh2 * [z2 > 0]
+  // dz2 = (dy W3) * [z2 > 0]    (lane -> i)
   for (int e = tid; e < MLP_ROWS * MLP_H; e += MLP_THREADS) {
     const int r = e / MLP_H, i = e % MLP_H;
     float s = 0.f;
-    for (int o = 0; o < k; ++o) s = fmaf(yy[r * MLP_MAX_K + o], W3[o * MLP_H + i], s);
+    for (int o = 0; o < k; ++o) s = fmaf(yy[r * MLP_MAX_K + o], W3[o * W3S + i], s);
     dh[e] = z2[e] > 0.f ? s : 0.f;
   }
   __syncthreads();
-  // dW2[o][i] = sum_r dz2[r][o] relu(z1[r][i]); db2
+  // dW2[o][i] = sum_r dz2[r][o] relu(z1[r][i]); db2       (lane -> i)
   for (int e = tid; e < MLP_H * MLP_H; e += MLP_THREADS) {
     const int o = e / MLP_H, i = e % MLP_H;
     float s = 0.f;
@@ -172,11 +185,11 @@ mlp_fwdbwd_kernel(const float* __restrict__ P, const float* __restrict__ X, cons
     for (int r = 0; r < MLP_ROWS; ++r) s += dh[r * MLP_H + o];
     g[L.ob2 + o] = s;
   }
-  // dz1 = (dz2 W2) * [z1 > 0], written over z2 (no longer needed)
+  // dz1 = (dz2 W2) * [z1 > 0], written over z2 (no longer needed)   (lane -> i)
   for (int e = tid; e < MLP_ROWS * MLP_H; e += MLP_THREADS) {
     const int r = e / MLP_H, i = e % MLP_H;
     float s = 0.f;
-    for (int o = 0; o < MLP_H; ++o) s = fmaf(dh[r * MLP_H + o], W2[o * MLP_H + i], s);
+    for (int o = 0; o < MLP_H; ++o) s = fmaf(dh[r * MLP_H + o], W2[o * W2S + i], s);
     z2[e] = z1[e] > 0.f ? s : 0.f;
   }
   __syncthreads();
@@ -284,9 +297,10 @@ static MlpPlan mlp_plan(int n, int k, int d) {
 }
 
 static size_t fwdbwd_lds(int k) {
-  const MlpLayout L(k);
-  return ((size_t)((L.total + 3) & ~3) + MLP_ROWS * MLP_IN + 3 * MLP_ROWS * MLP_H +
-          MLP_ROWS * MLP_MAX_K) * 4;
+  (void)k;
+  return ((size_t)MLP_H * (MLP_IN + 1) + MLP_H * (MLP_H + 1) + MLP_MAX_K * (MLP_H + 1) + 2 * MLP_H +
+          MLP_MAX_K + MLP_ROWS * MLP_IN + 2 * MLP_ROWS * MLP_H + MLP_ROWS * MLP_MAX_K +
+          MLP_ROWS * MLP_H) * 4;
 }
 
 static hipError_t launch_fwdbwd(const float* P, const float* X, const float* Y, int n, int k,

@@ -24,8 +24,19 @@ DEFAULT_TABLE = os.path.join(HERE, "data", "sweep_f32_mi355x.npz")
 DTYPE_NAMES = {"f32": 0, "bf16": 1, "fp8": 2}
 
 
-def table_path(dtype_name: str) -> str:
-    return os.path.join(HERE, "data", f"sweep_{dtype_name}_mi355x.npz")
+def table_path(dtype_name: str, problem_set: str = "sweep") -> str:
+    return os.path.join(HERE, "data", f"{problem_set}_{dtype_name}_mi355x.npz")
+
+
+def problem_set(name: str):
+    """Problems of a named set: 'sweep' (300 shapes x 4 layouts) or 'conv' (the
+    GEMMs of a VGG16-style conv stack, im2col and Winograd lowerings, NN)."""
+    import synth
+    if name == "sweep":
+        return synth.sweep_problems()
+    if name == "conv":
+        return [(c["M"], c["N"], c["K"], c["batch"], 0, 0) for c in synth.conv_shapes()]
+    raise ValueError(name)
 DEPLOY_SPEC = os.path.join(HERE, "data", "deploy_f32.json")
 DEPLOY_LIB = os.path.join(HERE, "libkt_deploy.so")
 
@@ -46,13 +57,13 @@ def save_table(path, time_ns, problems, configs, meta):
 
 
 def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
-              cut_factor=8.0, warmup=0, limit=None, log=print, dtype=0):
+              cut_factor=8.0, warmup=0, limit=None, log=print, dtype=0, set_name="sweep"):
     import torch
 
     import synth
     from . import Handle
     h = Handle(0)
-    problems = synth.sweep_problems()
+    problems = problem_set(set_name)
     if limit:
         problems = problems[:limit]
     configs = h.configs(dtype)
@@ -107,6 +118,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("sweep")
     s.add_argument("--dtype", default="f32", choices=sorted(DTYPE_NAMES))
+    s.add_argument("--set", default="sweep", choices=["sweep", "conv"])
     s.add_argument("--out", default=None)
     s.add_argument("--budget-s", type=float, default=900.0)
     s.add_argument("--limit", type=int, default=None)
@@ -118,7 +130,8 @@ def main(argv=None):
     d.add_argument("--no-build", action="store_true")
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
-        run_sweep(a.out or table_path(a.dtype), a.budget_s, limit=a.limit, dtype=DTYPE_NAMES[a.dtype])
+        run_sweep(a.out or table_path(a.dtype, a.set), a.budget_s, limit=a.limit,
+                  dtype=DTYPE_NAMES[a.dtype], set_name=a.set)
     elif a.cmd == "deploy":
         # choose the k kernels by GPU k-means over the training problems of the
         # measured table, record them, and build the library with only those
