@@ -41,15 +41,16 @@ def f32_configs():
 
 
 LP_TILES = (32, 64, 128, 256)
-LP_THREAD_TILES = (4, 8)
-LP_K_TILES = (32, 64, 128)
+LP_THREAD_TILES = (4, 8, 16)
+BF16_K_TILES = (32, 64, 128)     # multiples of the BF16 MFMA depth (16)
+FP8_K_TILES = (64, 128, 256)     # multiples of the FP8 MFMA depth (64)
 
 
-def lp_configs():
-    """Ordered (bm, bn, t, bk) list shared by the BF16 and FP8 families: wave
-    blocks of 32x32 (t = 4) or 64x64 (t = 8) MFMA outputs, 1..16 waves, and
-    double-buffered LDS stages (rows padded by 16 bytes) within 160 KiB at
-    two bytes per element."""
+def _lp_configs(k_tiles, elem_bytes):
+    """Ordered (bm, bn, t, bk) list of a low-precision family: wave blocks of
+    32x32 (t = 4), 64x64 (t = 8) or 128x128 (t = 16) MFMA outputs, 1..16
+    waves, and double-buffered LDS stages (rows padded by 16 bytes) within
+    160 KiB."""
     out = []
     for t in LP_THREAD_TILES:
         wt = 8 * t
@@ -60,23 +61,32 @@ def lp_configs():
                 waves = (bm * bn) // (wt * wt)
                 if not 1 <= waves <= 16:
                     continue
-                for bk in LP_K_TILES:
-                    if 2 * (bm + bn) * (bk + 8) * 2 > 160 * 1024:
+                for bk in k_tiles:
+                    if 2 * (bm + bn) * (bk * elem_bytes + 16) > 160 * 1024:
                         continue
                     out.append((bm, bn, t, bk))
     return out
 
 
+def bf16_configs():
+    return _lp_configs(BF16_K_TILES, 2)
+
+
+def fp8_configs():
+    return _lp_configs(FP8_K_TILES, 1)
+
+
 DTYPES = (  # (name, config list, launcher template)
     ("f32", f32_configs, "launch_gemm_f32<{bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_f32.hpp"),
-    ("bf16", lp_configs, "launch_gemm_lp<2, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
-    ("fp8", lp_configs, "launch_gemm_lp<1, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
+    ("bf16", bf16_configs, "launch_gemm_lp<2, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
+    ("fp8", fp8_configs, "launch_gemm_lp<1, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
 )
 
 
 def _chunks(seq, n):
-    size = (len(seq) + n - 1) // n
-    return [seq[i:i + size] for i in range(0, len(seq), size)]
+    """Round-robin split (neighbouring configurations cost alike to compile,
+    so interleaving balances the parallel build)."""
+    return [seq[i::n] for i in range(n) if seq[i::n]]
 
 
 def generate(out_dir: str, f32_ids=None, lp_ids=None, n_parts: int = 24, lp_parts: int = 12):
@@ -141,4 +151,4 @@ if __name__ == "__main__":
     c = f32_configs()
     by_t = {t: sum(1 for x in c if x[2] == t) for t in THREAD_TILES}
     print("f32", len(c), by_t)
-    print("bf16/fp8", len(lp_configs()))
+    print("bf16", len(bf16_configs()), "fp8", len(fp8_configs()))

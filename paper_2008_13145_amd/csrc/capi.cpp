@@ -109,16 +109,12 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
   g.scaleA = scaleA; g.scaleB = scaleB;
   g.vecA = aligned(A, lda, sA);
   g.vecB = aligned(B, ldb, sB);
-  const int64_t max_y = 65535;
-  for (int64_t b0 = 0; b0 < s->batch; b0 += max_y) {
-    const int64_t nb = (s->batch - b0) < max_y ? (s->batch - b0) : max_y;
-    g.batch = nb;
-    g.A = (const char*)A + b0 * sA * eb;
-    g.B = (const char*)B + b0 * sB * eb;
-    g.C = C + b0 * sC;
-    hipError_t e = fn(g, stream);
-    if (e != hipSuccess) return hip_fail(h, e, "kernel launch");
-  }
+  g.batch = s->batch;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  hipError_t e = fn(g, stream);   // splits huge batches into several grids
+  if (e != hipSuccess) return hip_fail(h, e, "kernel launch");
   return KT_OK;
 }
 

@@ -41,17 +41,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Work-group id -> (tile_m, tile_n).  Consecutive work-group ids land on
-// different XCDs (round robin over 8), so the id is first remapped to give
-// each XCD a contiguous range of tiles; tiles are then walked in groups of
-// 8 tile-rows so that neighbours share A row panels and B column panels in
-// that XCD's L2.
-__device__ __forceinline__ void tile_coords(int64_t pid, int tiles_m, int tiles_n, int& tm,
-                                            int& tn) {
+// Work-group id -> (batch item, tile_m, tile_n).  The grid is one flat range
+// over (batch item, tile).  Consecutive work-group ids land on different XCDs
+// (round robin over 8), so the id is first remapped to give each XCD a
+// contiguous range of that flat space -- whole batch items, or neighbouring
+// tiles of one item; tiles of an item are then walked in groups of 8
+// tile-rows so that neighbours share A row panels and B column panels in that
+// XCD's L2.
+__device__ __forceinline__ void block_coords(int64_t pid, int tiles_m, int tiles_n,
+                                             int64_t batch, int& tm, int& tn, int64_t& bz) {
   const int64_t nt = (int64_t)tiles_m * tiles_n;
-  const int64_t per = nt / 8;
+  const int64_t per = nt * batch / 8;
   int64_t t = pid;
   if (pid < per * 8) t = (pid % 8) * per + pid / 8;
+  bz = t / nt;
+  t -= bz * nt;
   const int64_t group = 8;
   const int64_t width = group * tiles_n;
   const int64_t gid = t / width;
@@ -60,6 +64,32 @@ __device__ __forceinline__ void tile_coords(int64_t pid, int tiles_m, int tiles_
   const int64_t r = t % width;
   tm = (int)(first_m + r % gsz);
   tn = (int)(r / gsz);
+}
+
+// Launches a GEMM family kernel over a flat (batch item, tile) grid, in as
+// many launches as the 32-bit work-item count of one grid dimension needs.
+// EB is the element size of A and B in bytes.
+template <int EB, typename Kernel>
+hipError_t launch_flat(Kernel kernel, const GemmArgs& a, int bm, int bn, int nt_threads,
+                       hipStream_t stream) {
+  GemmArgs g = a;
+  g.tiles_m = (int)((a.M + bm - 1) / bm);
+  g.tiles_n = (int)((a.N + bn - 1) / bn);
+  const int64_t nt = (int64_t)g.tiles_m * g.tiles_n;
+  const int64_t max_blocks = (int64_t)0xFFFFFFFFu / nt_threads;
+  if (nt > max_blocks) return hipErrorInvalidConfiguration;
+  const int64_t per_launch = max_blocks / nt;
+  for (int64_t b0 = 0; b0 < a.batch; b0 += per_launch) {
+    const int64_t nb = (a.batch - b0) < per_launch ? (a.batch - b0) : per_launch;
+    g.batch = nb;
+    g.A = static_cast<const char*>(a.A) + b0 * a.sA * EB;
+    g.B = static_cast<const char*>(a.B) + b0 * a.sB * EB;
+    g.C = a.C + b0 * a.sC;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)(nt * nb)), dim3(nt_threads), 0, stream, g);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Global -> register staging of one ROWS x COLS tile whose COLS dimension is
@@ -156,8 +186,8 @@ gemm_f32_kernel(GemmArgs args) {
   const int wn0 = (wave % Cfg::WAVES_N) * WT;
 
   int tm, tn;
-  tile_coords(blockIdx.x, args.tiles_m, args.tiles_n, tm, tn);
-  const int64_t bz = blockIdx.y;
+  int64_t bz;
+  block_coords(blockIdx.x, args.tiles_m, args.tiles_n, args.batch, tm, tn, bz);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int64_t M = args.M, N = args.N, K = args.K;
   const float* __restrict__ Ag = static_cast<const float*>(args.A) + bz * args.sA;
@@ -328,12 +358,7 @@ gemm_f32_kernel(GemmArgs args) {
 template <int BM, int BN, int T, int BK, int TA, int TB>
 hipError_t launch_gemm_f32(const GemmArgs& a, hipStream_t stream) {
   using Cfg = GemmF32Cfg<BM, BN, T, BK, TA, TB>;
-  GemmArgs g = a;
-  g.tiles_m = (int)((a.M + BM - 1) / BM);
-  g.tiles_n = (int)((a.N + BN - 1) / BN);
-  dim3 grid((unsigned)((int64_t)g.tiles_m * g.tiles_n), (unsigned)a.batch, 1);
-  hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, T, BK, TA, TB>), grid, dim3(Cfg::NT), 0, stream, g);
-  return hipGetLastError();
+  return launch_flat<4>(gemm_f32_kernel<BM, BN, T, BK, TA, TB>, a, BM, BN, Cfg::NT, stream);
 }
 
 }  // namespace kt

@@ -3,16 +3,21 @@
 // with s = 1 for BF16 and s = 1 / (scaleA * scaleB) for per-tensor-scaled FP8.
 //
 // Same configuration knobs as the FP32 family (work-group tile BM x BN, per
-// wave an (8T) x (8T) block, K depth BK per LDS stage), with T in {4, 8}:
-// T = 4 is one 32x32 MFMA block per wave, T = 8 a 2x2 grid of them.
-// v_mfma_f32_32x32x16_bf16 / _fp8_fp8 take 8 consecutive K values per lane
-// (lane l: row l % 32, K offset 8 * (l / 32)), so both operands sit in LDS
-// with K contiguous ([m][k], [n][k]) and every fragment is one 16- (BF16) or
-// 8-byte (FP8) LDS read.  Rows are padded by 16 bytes so the 32 rows a
-// half-wave reads start on different banks.  An operand stored contiguous
-// along K is copied into LDS with 16-byte vectors; one stored contiguous
-// along M / N is transposed in registers, 8 K rows at a time, and written as
-// K-contiguous vectors.
+// wave an (8T) x (8T) block, K depth BK per LDS stage), with T in {4, 8, 16}:
+// T = 4 is one 32x32 MFMA block per wave, T = 8 a 2x2 and T = 16 a 4x4 grid
+// of them (the 4x4 grid keeps its 256 accumulators in AGPRs and halves the
+// LDS bytes read per MFMA against the 2x2 grid).
+// BF16 runs v_mfma_f32_32x32x16_bf16 (8 consecutive K values per lane, lane
+// l: row l % 32, K offset 8 * (l / 32)); FP8 runs the 64-deep
+// v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales (32 K bytes per
+// lane, K offset 32 * (l / 32)).  A and B fragments take K in the same lane
+// order, so each product pairs the right elements whatever order the unit
+// sums them in.  Both operands sit in LDS with K contiguous ([m][k], [n][k])
+// and every fragment is one (BF16) or two (FP8) 16-byte LDS reads.  Rows are
+// padded by 16 bytes so the rows a read phase touches start on different
+// banks.  An operand stored contiguous along K is copied into LDS with
+// 16-byte vectors; one stored contiguous along M / N is transposed in
+// registers, 8 K rows at a time, and written as K-contiguous vectors.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,13 +31,15 @@ namespace kt {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8a16 __attribute__((ext_vector_type(8), aligned(16)));
 
 template <int EB>   // element bytes: 2 = BF16, 1 = FP8 e4m3
 struct LpElem;
 template <>
-struct LpElem<2> { typedef uint16_t T; };
+struct LpElem<2> { typedef uint16_t T; static constexpr int KSTEP = 16; };
 template <>
-struct LpElem<1> { typedef uint8_t T; };
+struct LpElem<1> { typedef uint8_t T; static constexpr int KSTEP = 64; };
 
 // Operand alignment modes (GemmArgs::vecA / vecB for the low-precision
 // kernels): 2 = every row starts on a 4-byte boundary; 1 = only the operand's
@@ -72,6 +79,16 @@ struct LpTileLoader {
                                        int64_t col0, int64_t row_lim, int64_t col_lim, int vec,
                                        int tid) {
     const bool full = vec == LP_ALIGN_ROWS && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
+    if (full) {   // interior tile: one straight run of 16-byte loads
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int c = tid + i * NT;
+        if (NV % NT != 0 && c >= NV) { v[i] = u32x4{0u, 0u, 0u, 0u}; continue; }
+        const int r = c / CV, q = (c % CV) * EPC;
+        v[i] = *reinterpret_cast<const u32x4u*>(base + (row0 + r) * ld + col0 + q);
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int c = tid + i * NT;
@@ -79,28 +96,24 @@ struct LpTileLoader {
       const int r = c / CV, q = (c % CV) * EPC;
       const int64_t gr = row0 + r, gc = col0 + q;
       const E* p = base + gr * ld + gc;
-      if (full) {
-        v[i] = *reinterpret_cast<const u32x4u*>(p);
-      } else {
-        u32x4 t = {0u, 0u, 0u, 0u};
-        if (gr < row_lim) {
-          if (vec == LP_ALIGN_ROWS && gc + EPC <= col_lim) {
-            t = *reinterpret_cast<const u32x4u*>(p);
-          } else if (vec == LP_ALIGN_BASE && gc + EPC + 4 / EB <= col_lim) {
-            uint32_t o[4];
-            load_realigned<4>(p, o);
-            t = u32x4{o[0], o[1], o[2], o[3]};
-          } else {
-            // element by element, packed little-endian into the chunk
+      u32x4 t = {0u, 0u, 0u, 0u};
+      if (gr < row_lim) {
+        if (vec == LP_ALIGN_ROWS && gc + EPC <= col_lim) {
+          t = *reinterpret_cast<const u32x4u*>(p);
+        } else if (vec == LP_ALIGN_BASE && gc + EPC + 4 / EB <= col_lim) {
+          uint32_t o[4];
+          load_realigned<4>(p, o);
+          t = u32x4{o[0], o[1], o[2], o[3]};
+        } else {
+          // element by element, packed little-endian into the chunk
 #pragma unroll
-            for (int e = 0; e < EPC; ++e) {
-              const uint32_t x = (gc + e < col_lim) ? (uint32_t)p[e] : 0u;
-              t[(e * EB) / 4] |= x << (8 * ((e * EB) % 4));
-            }
+          for (int e = 0; e < EPC; ++e) {
+            const uint32_t x = (gc + e < col_lim) ? (uint32_t)p[e] : 0u;
+            t[(e * EB) / 4] |= x << (8 * ((e * EB) % 4));
           }
         }
-        v[i] = t;
       }
+      v[i] = t;
     }
   }
 
@@ -148,6 +161,20 @@ struct LpTransposeLoader {
                                        int64_t col0, int64_t k_lim, int64_t col_lim, int vec,
                                        int tid) {
     const bool full = vec == LP_ALIGN_ROWS && (k0 + KROWS <= k_lim) && (col0 + COLS <= col_lim);
+    if (full) {   // interior tile: one straight run of loads
+#pragma unroll
+      for (int i = 0; i < UPT; ++i) {
+        const int u = tid + i * NT;
+        if (NU % NT != 0 && u >= NU) continue;
+        const int ku = u / CU, cu = u % CU;
+        const E* p0 = base + (k0 + ku * 8) * ld + col0 + cu * EPC;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+          for (int d = 0; d < WD; ++d) v[i][r][d] = reinterpret_cast<const uint32_t*>(p0 + r * ld)[d];
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
       const int u = tid + i * NT;
@@ -159,7 +186,7 @@ struct LpTransposeLoader {
         const int64_t gk = k0 + ku * 8 + r;
         const E* p = base + gk * ld + gc;
         const bool in_rows = gk < k_lim;
-        if (full || (vec == LP_ALIGN_ROWS && in_rows && gc + EPC <= col_lim)) {
+        if (vec == LP_ALIGN_ROWS && in_rows && gc + EPC <= col_lim) {
 #pragma unroll
           for (int d = 0; d < WD; ++d) v[i][r][d] = reinterpret_cast<const uint32_t*>(p)[d];
         } else if (vec == LP_ALIGN_BASE && in_rows && gc + EPC + 4 / EB <= col_lim) {
@@ -224,28 +251,35 @@ struct GemmLpCfg {
   static constexpr int A_STAGE = BM * LDK;           // elements
   static constexpr int B_STAGE = BN * LDK;
   static constexpr int LDS_BYTES = 2 * (A_STAGE + B_STAGE) * EB;
-  static_assert(T == 4 || T == 8, "low-precision wave blocks are 32x32 or 64x64");
+  static_assert(T == 4 || T == 8 || T == 16, "low-precision wave blocks are 32x32, 64x64 or 128x128");
   static_assert(BM % WT == 0 && BN % WT == 0, "tile must hold whole wave blocks");
   static_assert(WAVES >= 1 && WAVES <= 16, "1..16 waves per work-group");
-  static_assert(BK % 16 == 0, "BK multiple of the MFMA K (16)");
+  static_assert(BK % LpElem<EB>::KSTEP == 0, "BK multiple of the MFMA depth");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
+// One lane's operand fragment for one MFMA: 8 BF16 values (16 bytes) or
+// 32 FP8 codes (32 bytes), read from LDS as one or two 16-byte reads.
 template <int EB>
-__device__ __forceinline__ void lp_mfma(const void* a, const void* b, f32x16& c);
-
+struct LpFrag;
 template <>
-__device__ __forceinline__ void lp_mfma<2>(const void* a, const void* b, f32x16& c) {
-  const bf16x8 va = *reinterpret_cast<const bf16x8*>(a);
-  const bf16x8 vb = *reinterpret_cast<const bf16x8*>(b);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va, vb, c, 0, 0, 0);
+struct LpFrag<2> {
+  bf16x8 v;
+  __device__ __forceinline__ void read(const void* p) { v = *reinterpret_cast<const bf16x8*>(p); }
+};
+template <>
+struct LpFrag<1> {
+  i32x8 v;
+  __device__ __forceinline__ void read(const void* p) { v = *reinterpret_cast<const i32x8a16*>(p); }
+};
+
+__device__ __forceinline__ void lp_mfma(const LpFrag<2>& a, const LpFrag<2>& b, f32x16& c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b.v, c, 0, 0, 0);
 }
 
-template <>
-__device__ __forceinline__ void lp_mfma<1>(const void* a, const void* b, f32x16& c) {
-  const long va = *reinterpret_cast<const long*>(a);
-  const long vb = *reinterpret_cast<const long*>(b);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(va, vb, c, 0, 0, 0);
+// Operand formats 0 / 0 = e4m3 for A and B; block scales 127 = 2^0 (E8M0).
+__device__ __forceinline__ void lp_mfma(const LpFrag<1>& a, const LpFrag<1>& b, f32x16& c) {
+  c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a.v, b.v, c, 0, 0, 0, 127, 0, 127);
 }
 
 // One BM x BN output tile (tile row tm, tile column tn) of batch item bz:
@@ -305,31 +339,35 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int r32 = lane & 31, kh = (lane >> 5) * 8;
+  constexpr int KSTEP = LpElem<EB>::KSTEP;
+  const int r32 = lane & 31, kh = (lane >> 5) * (KSTEP / 2);
   const int nk = (int)((K + BK - 1) / BK);
   if (nk > 0) {
     load_stage(0);
     store_stage(0);
     __syncthreads();
   }
+  // Fragments are double-buffered in registers: the reads for MFMA step
+  // s + 1 are issued before the MFMAs of step s, so LDS latency hides behind
+  // them even at one wave per SIMD.
+  constexpr int NKK = BK / KSTEP;
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
     const E* as = As + buf * Cfg::A_STAGE;
     const E* bs = Bs + buf * Cfg::B_STAGE;
+    if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      const E* ap[SUB];
-      const E* bp[SUB];
+    for (int s = 0; s < NKK; ++s) {
+      LpFrag<EB> fa[SUB], fb[SUB];
 #pragma unroll
       for (int i = 0; i < SUB; ++i) {
-        ap[i] = as + (wm0 + 32 * i + r32) * LDK + kk + kh;
-        bp[i] = bs + (wn0 + 32 * i + r32) * LDK + kk + kh;
+        fa[i].read(as + (wm0 + 32 * i + r32) * LDK + s * KSTEP + kh);
+        fb[i].read(bs + (wn0 + 32 * i + r32) * LDK + s * KSTEP + kh);
       }
 #pragma unroll
       for (int i = 0; i < SUB; ++i)
 #pragma unroll
-        for (int j = 0; j < SUB; ++j) lp_mfma<EB>(ap[i], bp[j], acc[i][j]);
+        for (int j = 0; j < SUB; ++j) lp_mfma(fa[i], fb[j], acc[i][j]);
     }
     if (kt + 1 < nk) store_stage(buf ^ 1);
     __syncthreads();
@@ -363,19 +401,15 @@ gemm_lp_kernel(GemmArgs args) {
   typedef typename LpElem<EB>::T E;
   __shared__ __attribute__((aligned(16))) E lds[Cfg::LDS_BYTES / EB];
   int tm, tn;
-  tile_coords(blockIdx.x, args.tiles_m, args.tiles_n, tm, tn);
-  lp_tile<EB, BM, BN, T, BK, TA, TB>(args, tm, tn, (int64_t)blockIdx.y, lds);
+  int64_t bz;
+  block_coords(blockIdx.x, args.tiles_m, args.tiles_n, args.batch, tm, tn, bz);
+  lp_tile<EB, BM, BN, T, BK, TA, TB>(args, tm, tn, bz, lds);
 }
 
 template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
 hipError_t launch_gemm_lp(const GemmArgs& a, hipStream_t stream) {
   using Cfg = GemmLpCfg<EB, BM, BN, T, BK, TA, TB>;
-  GemmArgs g = a;
-  g.tiles_m = (int)((a.M + BM - 1) / BM);
-  g.tiles_n = (int)((a.N + BN - 1) / BN);
-  dim3 grid((unsigned)((int64_t)g.tiles_m * g.tiles_n), (unsigned)a.batch, 1);
-  hipLaunchKernelGGL((gemm_lp_kernel<EB, BM, BN, T, BK, TA, TB>), grid, dim3(Cfg::NT), 0, stream, g);
-  return hipGetLastError();
+  return launch_flat<EB>(gemm_lp_kernel<EB, BM, BN, T, BK, TA, TB>, a, BM, BN, Cfg::NT, stream);
 }
 
 }  // namespace kt

@@ -5,9 +5,9 @@ the FP64 oracle on the original FP32 operands <= 1e-2 (BF16) and <= 4e-2
 (FP8).  The kernel itself is checked tighter against the oracle on the
 dequantized operands: BF16 within the FP32-accumulation bound; FP8 within a
 relative Frobenius error of 1e-3, because gfx950's FP8 MFMA
-(v_mfma_f32_32x32x16_fp8_fp8) does not accumulate at full FP32 precision
-(measured: sums land on a grid of about 12 significant bits), and every FP8
-configuration must give the same bits.  BF16 is also checked bit for bit
+(v_mfma_scale_f32_32x32x64_f8f6f4, unit block scales) does not accumulate at
+full FP32 precision (measured: one instruction's error is about
+2^-12 * sum |terms|), and every FP8 configuration must give the same bits.  BF16 is also checked bit for bit
 where every value and partial sum is exact."""
 import math
 
@@ -186,9 +186,9 @@ def test_all_configs_exact_integers_bf16(gpu, ta, tb):
 
 @pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
 def test_fp8_one_mfma_block_exact(gpu, ta, tb):
-    """FP8 with K = 16 (one MFMA block) and values k * 64, k in [-7, 7]
-    (exact e4m3 codes after the power-of-two scale 448 / 7 = 64): the single
-    block's sum is exact, so every configuration equals the oracle."""
+    """FP8 with K = 16 (inside one 64-deep MFMA) and values k * 64, k in
+    [-7, 7] (exact e4m3 codes after the power-of-two scale 448 / 7 = 64): the
+    sum is exact, so every configuration equals the oracle."""
     h, torch = gpu
     M, N, K, bt = 70, 45, 16, 1
     rng = np.random.default_rng(10 + ta * 2 + tb)
