@@ -47,18 +47,31 @@ struct LpElem<1> { typedef uint8_t T; static constexpr int KSTEP = 64; };
 enum { LP_ALIGN_NONE = 0, LP_ALIGN_BASE = 1, LP_ALIGN_ROWS = 2 };
 
 // WD dwords from byte address p, which need not be 4-byte aligned: the
-// dword-aligned window covering them (one dword more) is read and realigned
-// with v_alignbyte.  The caller guarantees that the window lies inside valid
-// memory (the window never starts below a 4-byte aligned base and its extra
-// bytes are columns of the same row).
+// dword-aligned window covering them (one dword more) is read with the widest
+// 4-byte-aligned vector loads and realigned with v_alignbyte.  The caller
+// guarantees that the window lies inside valid memory (the window never
+// starts below a 4-byte aligned base and its extra bytes are columns of the
+// same row).
 template <int WD>
 __device__ __forceinline__ void load_realigned(const void* p, uint32_t* out) {
+  static_assert(WD == 1 || WD == 2 || WD == 4, "window of 1, 2 or 4 dwords");
+  typedef uint32_t u32x2u __attribute__((ext_vector_type(2), aligned(4)));
   const uintptr_t a = (uintptr_t)p;
   const uint32_t mis = (uint32_t)(a & 3u);
   const uint32_t* w = reinterpret_cast<const uint32_t*>(a - mis);
   uint32_t t[WD + 1];
-#pragma unroll
-  for (int d = 0; d <= WD; ++d) t[d] = w[d];
+  if (WD == 4) {
+    const u32x4u lo = *reinterpret_cast<const u32x4u*>(w);
+    t[0] = lo[0]; t[1] = lo[1]; t[2] = lo[2]; t[3] = lo[3];
+    t[WD] = w[4];
+  } else if (WD == 2) {
+    const u32x2u lo = *reinterpret_cast<const u32x2u*>(w);
+    t[0] = lo[0]; t[1] = lo[1];
+    t[WD] = w[2];
+  } else {
+    const u32x2u lo = *reinterpret_cast<const u32x2u*>(w);
+    t[0] = lo[0]; t[1] = lo[1];
+  }
 #pragma unroll
   for (int d = 0; d < WD; ++d) out[d] = __builtin_amdgcn_alignbyte(t[d + 1], t[d], mis);
 }
@@ -78,14 +91,29 @@ struct LpTileLoader {
   __device__ __forceinline__ void load(const E* __restrict__ base, int64_t ld, int64_t row0,
                                        int64_t col0, int64_t row_lim, int64_t col_lim, int vec,
                                        int tid) {
-    const bool full = vec == LP_ALIGN_ROWS && (row0 + ROWS <= row_lim) && (col0 + COLS <= col_lim);
-    if (full) {   // interior tile: one straight run of 16-byte loads
+    const bool rows_in = row0 + ROWS <= row_lim;
+    if (vec == LP_ALIGN_ROWS && rows_in && col0 + COLS <= col_lim) {
+      // interior tile, rows on 4-byte boundaries: one 16-byte load per chunk
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int c = tid + i * NT;
         if (NV % NT != 0 && c >= NV) { v[i] = u32x4{0u, 0u, 0u, 0u}; continue; }
         const int r = c / CV, q = (c % CV) * EPC;
         v[i] = *reinterpret_cast<const u32x4u*>(base + (row0 + r) * ld + col0 + q);
+      }
+      return;
+    }
+    if (vec == LP_ALIGN_BASE && rows_in && col0 + COLS + 4 / EB <= col_lim) {
+      // interior tile, rows off 4-byte boundaries: realigned windows, whose
+      // extra dword is still inside the row
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int c = tid + i * NT;
+        if (NV % NT != 0 && c >= NV) { v[i] = u32x4{0u, 0u, 0u, 0u}; continue; }
+        const int r = c / CV, q = (c % CV) * EPC;
+        uint32_t o[4];
+        load_realigned<4>(base + (row0 + r) * ld + col0 + q, o);
+        v[i] = u32x4{o[0], o[1], o[2], o[3]};
       }
       return;
     }
@@ -160,8 +188,9 @@ struct LpTransposeLoader {
   __device__ __forceinline__ void load(const E* __restrict__ base, int64_t ld, int64_t k0,
                                        int64_t col0, int64_t k_lim, int64_t col_lim, int vec,
                                        int tid) {
-    const bool full = vec == LP_ALIGN_ROWS && (k0 + KROWS <= k_lim) && (col0 + COLS <= col_lim);
-    if (full) {   // interior tile: one straight run of loads
+    const bool rows_in = k0 + KROWS <= k_lim;
+    if (vec == LP_ALIGN_ROWS && rows_in && col0 + COLS <= col_lim) {
+      // interior tile, rows on 4-byte boundaries: one straight run of loads
 #pragma unroll
       for (int i = 0; i < UPT; ++i) {
         const int u = tid + i * NT;
@@ -172,6 +201,19 @@ struct LpTransposeLoader {
         for (int r = 0; r < 8; ++r)
 #pragma unroll
           for (int d = 0; d < WD; ++d) v[i][r][d] = reinterpret_cast<const uint32_t*>(p0 + r * ld)[d];
+      }
+      return;
+    }
+    if (vec == LP_ALIGN_BASE && rows_in && col0 + COLS + 4 / EB <= col_lim) {
+      // interior tile, rows off 4-byte boundaries: realigned windows
+#pragma unroll
+      for (int i = 0; i < UPT; ++i) {
+        const int u = tid + i * NT;
+        if (NU % NT != 0 && u >= NU) continue;
+        const int ku = u / CU, cu = u % CU;
+        const E* p0 = base + (k0 + ku * 8) * ld + col0 + cu * EPC;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) load_realigned<WD>(p0 + r * ld, v[i][r]);
       }
       return;
     }
