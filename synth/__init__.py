@@ -84,12 +84,29 @@ def operand_seed(base: int, role: int) -> int:
     return mix64((base * 8 + role) & MASK64)
 
 
-def uniform_operand(seed: int, count: int, offset: int = 0) -> np.ndarray:
-    """``count`` FP32 values x(seed, offset + i) in [-1, 1), as a flat array."""
-    idx = np.arange(offset, offset + count, dtype=np.uint64)
+def _uniform_chunk(seed: int, offset: int, out: np.ndarray) -> None:
+    idx = np.arange(offset, offset + out.size, dtype=np.uint64)
     h = _mix_np(np.uint64(seed & MASK64) ^ idx)
     u24 = (h >> np.uint64(40)).astype(np.int64)
-    return (u24.astype(np.float64) * (2.0 ** -23) - 1.0).astype(np.float32)
+    out[:] = u24.astype(np.float64) * (2.0 ** -23) - 1.0
+
+
+def uniform_operand(seed: int, count: int, offset: int = 0, threads: int = 16) -> np.ndarray:
+    """``count`` FP32 values x(seed, offset + i) in [-1, 1), as a flat array.
+    Large requests are generated in chunks on a thread pool (numpy releases
+    the GIL); every element depends only on (seed, index), so the result does
+    not depend on the chunking."""
+    out = np.empty(count, dtype=np.float32)
+    chunk = 1 << 22
+    if count <= chunk or threads <= 1:
+        for c0 in range(0, count, chunk):
+            _uniform_chunk(seed, offset + c0, out[c0:c0 + chunk])
+        return out
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda c0: _uniform_chunk(seed, offset + c0, out[c0:c0 + chunk]),
+                    range(0, count, chunk)))
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -251,3 +251,20 @@ def test_large_shape_sampled(gpu):
         for i in range(bt):
             assert np.all(np.abs(C[i][rows, :] - ref_r[i]) <= tol[i]), c
             assert np.all(np.abs(C[i][:, cols] - ref_c[i]) <= tol[i]), c
+
+
+def test_batch_split_over_grids(gpu):
+    """A batch whose flat (batch item, tile) grid exceeds the 32-bit work-item
+    count of one launch (1024-thread work-groups, one tile per item) is split
+    over several grids; every item must still be computed."""
+    h, torch = gpu
+    M, N, K = 2, 3, 5
+    bt = 0xFFFFFFFF // 1024 + 7
+    a = synth.uniform_operand(synth.operand_seed(77, 0), bt * M * K).reshape(bt, M, K)
+    b = synth.uniform_operand(synth.operand_seed(77, 1), bt * K * N).reshape(bt, K, N)
+    c0 = np.zeros((bt, M, N), np.float32)
+    cfg = h.configs().index((128, 128, 4, 32))      # 16 waves = 1024 threads
+    got = _run(h, torch, a, b, np.full_like(c0, np.nan), 0, 0, 1.0, 0.0, cfg)
+    ref = _oracle(a, b, c0, 1.0, 0.0)
+    assert not np.isnan(got).any()
+    assert np.all(np.abs(got - ref) <= _bound(a, b, c0, 1.0, 0.0))
