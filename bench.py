@@ -113,8 +113,9 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
         tl = TL.min(axis=1).astype(np.float64)
         ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), TL.shape[1], k, 10)
         pws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-        chosen = h.prune(TL[tr_rows], k, norm=kt.NORM_RELATIVE, seed=synth.SEED, n_init=10,
-                         max_iter=300, workspace=pws, ws_bytes=ws_bytes, stream=stream)["chosen"]
+        sel = tune.select_pruning(h, TL[tr_rows], k, synth.SEED, workspace=pws, ws_bytes=ws_bytes,
+                                  stream=stream)
+        chosen = sel["chosen"]
         h.fit_selector(kt.SEL_DT_B, [problems[r] for r in tr_rows], TL[tr_rows], chosen, dtype=dt)
         picks = [h.select(*p, dtype=dt) for p in problems]
         ratio = tl / TL[np.arange(len(problems)), picks]
@@ -151,6 +152,7 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
             "dt_b_pct_of_optimal_test": round(100 * _geomean(ratio[te_rows]), 2),
             "kmeans_ceiling_test": round(100 * _geomean(ceil), 2),
             "chosen": [list(h.get_config(c, dt)) for c in chosen],
+            "normalization": sel["norm_name"], "train_ceiling_by_normalization": sel["train_ceiling"],
             "accuracy_bound_rel_frobenius": 1e-2 if dt == kt.BF16 else 4e-2,
         }
         del lp
@@ -229,13 +231,17 @@ def main(argv=None):
     k = a.k
     ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), n_cfg, max(k, 15), 10)
     pws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    # the normalization (section 3.4) is chosen on the training rows
+    sel = tune.select_pruning(h, T[tr_rows], k, synth.SEED, workspace=pws, ws_bytes=ws_bytes,
+                              stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pr = h.prune(T[tr_rows], k, norm=kt.NORM_RELATIVE, seed=synth.SEED, n_init=10, max_iter=300,
+    pr = h.prune(T[tr_rows], k, norm=sel["norm"], seed=synth.SEED, n_init=10, max_iter=300,
                  workspace=pws, ws_bytes=ws_bytes, stream=stream)
     prune_ms = (time.perf_counter() - t0) * 1e3
     chosen = pr["chosen"]
-    _log(f"bench: pruned to {chosen} in {prune_ms:.1f} ms")
+    assert chosen == sel["chosen"]
+    _log(f"bench: pruned to {chosen} ({sel['norm_name']} normalization) in {prune_ms:.1f} ms")
     topn = h.prune_topn(T[tr_rows], k, workspace=pws, ws_bytes=ws_bytes, stream=stream)
 
     t_best = T.min(axis=1)
@@ -361,6 +367,7 @@ def main(argv=None):
                         f"deployed path (selector {a.selector} over k={k} k-means-pruned kernels)",
             "problems": n_prob, "gflop_per_step": round(total_flops / 1e9, 3),
             "k": k, "selector": a.selector, "chosen": [list(cfgs[c]) for c in chosen],
+            "normalization": sel["norm_name"], "train_ceiling_by_normalization": sel["train_ceiling"],
             "train_test_shapes": [len(train), len(test)],
         },
         "pct_mfma_peak": round(100 * value / FP32_PEAK_TFLOPS, 2),

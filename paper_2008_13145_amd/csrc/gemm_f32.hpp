@@ -163,6 +163,19 @@ struct GemmF32Cfg {
   static constexpr int A_STAGE = BK * LDA_S;
   static constexpr int B_STAGE = BK * LDB_S;
   static constexpr int LDS_FLOATS = 2 * (A_STAGE + B_STAGE);
+  // Occupancy target (waves per SIMD): what the LDS footprint allows (160 KiB
+  // per CU, 4 SIMDs), capped by an estimate of the registers a wave needs
+  // (accumulators, one stage of MFMA operands, the prefetched stage and a
+  // fixed allowance for addresses), so the register budget it implies does
+  // not force spills.  It lets the T = 8 kernels trade AGPRs for occupancy.
+  static constexpr int WG_PER_CU = (160 * 1024) / (LDS_FLOATS * 4) < 16 ? (160 * 1024) / (LDS_FLOATS * 4) : 16;
+  static constexpr int OCC_LDS = (WG_PER_CU * WAVES) / 4;
+  static constexpr int ACC_REGS = T == 1 ? 4 : T * T;
+  static constexpr int OPS_REGS = T <= 2 ? 2 * (BK / 4) : T == 4 ? BK : 4 * (BK / 2 > 16 ? 16 : BK / 2);
+  static constexpr int PREF_REGS = 4 * ((BM * BK / 4 + NT - 1) / NT + (BN * BK / 4 + NT - 1) / NT);
+  static constexpr int OCC_REG = 512 / (ACC_REGS + OPS_REGS + PREF_REGS + 40);
+  static constexpr int OCC_MIN = OCC_LDS < OCC_REG ? OCC_LDS : OCC_REG;
+  static constexpr int OCC = OCC_MIN < 1 ? 1 : OCC_MIN > 8 ? 8 : OCC_MIN;
   static_assert(BM % WT == 0 && BN % WT == 0, "tile must hold whole wave blocks");
   static_assert(WAVES >= 1 && WAVES <= 16, "1..16 waves per work-group");
   static_assert(LDS_FLOATS * 4 <= 160 * 1024, "LDS budget");
@@ -171,6 +184,7 @@ struct GemmF32Cfg {
 
 template <int BM, int BN, int T, int BK, int TA, int TB>
 __global__ void __launch_bounds__(BM * BN / (T * T))
+__attribute__((amdgpu_waves_per_eu(GemmF32Cfg<BM, BN, T, BK, TA, TB>::OCC, 8)))
 gemm_f32_kernel(GemmArgs args) {
   using Cfg = GemmF32Cfg<BM, BN, T, BK, TA, TB>;
   constexpr int NT = Cfg::NT;

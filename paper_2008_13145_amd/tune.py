@@ -41,6 +41,33 @@ DEPLOY_SPEC = os.path.join(HERE, "data", "deploy_f32.json")
 DEPLOY_LIB = os.path.join(HERE, "libkt_deploy.so")
 
 
+NORM_NAMES = ("relative", "raw_cutoff", "std_cutoff", "sigmoid")
+
+
+def select_pruning(h, T_train, k, seed, n_init=10, max_iter=300, workspace=None, ws_bytes=0,
+                   stream=None):
+    """k-means pruning (section 4.1) under each normalization of section 3.4,
+    keeping the one whose chosen set scores best on the training rows by the
+    paper's own measure: the geometric mean over rows of t_best / (fastest
+    chosen kernel's time).  Ties keep the earlier normalization.  Returns
+    {"norm": index, "norm_name", "chosen", "inertia", "train_ceiling": {name:
+    score}}."""
+    T_train = np.asarray(T_train, dtype=np.int64)
+    t_best = T_train.min(axis=1).astype(np.float64)
+    best = None
+    scores = {}
+    for norm, name in enumerate(NORM_NAMES):
+        res = h.prune(T_train, k, norm=norm, seed=seed, n_init=n_init, max_iter=max_iter,
+                      workspace=workspace, ws_bytes=ws_bytes, stream=stream)
+        chosen = [int(c) for c in res["chosen"]]
+        score = float(np.exp(np.mean(np.log(t_best / T_train[:, chosen].min(axis=1)))))
+        scores[name] = round(score, 6)
+        if best is None or score > best[0]:
+            best = (score, norm, chosen, int(res["inertia"]))
+    return {"norm": best[1], "norm_name": NORM_NAMES[best[1]], "chosen": best[2],
+            "inertia": best[3], "train_ceiling": scores}
+
+
 def load_table(path):
     """(time_ns int64 [P][C], problems int64 [P][6], configs int32 [C][4], meta dict)."""
     with np.load(path, allow_pickle=False) as z:
@@ -138,20 +165,19 @@ def main(argv=None):
         import torch
 
         import synth
-        from . import NORM_RELATIVE, Handle, build
+        from . import Handle, build
         T, P, C, meta = load_table(a.table)
         train, _ = synth.train_test_split()
         rows = synth.rows_of_shapes(train)
         h = Handle(0)
         ws_bytes = Handle.prune_workspace_bytes(len(rows), T.shape[1], a.k, 10)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-        res = h.prune(T[rows], a.k, norm=NORM_RELATIVE, seed=synth.SEED, n_init=10, max_iter=300,
-                      workspace=ws, ws_bytes=ws_bytes)
+        res = select_pruning(h, T[rows], a.k, synth.SEED, workspace=ws, ws_bytes=ws_bytes)
         chosen = res["chosen"]
         spec = dict(dtype="f32", k=a.k, chosen=chosen, configs=[list(map(int, C[i])) for i in chosen],
-                    norm="relative", seed=synth.SEED, n_init=10, max_iter=300,
-                    table=os.path.relpath(a.table, HERE), device=meta.get("device"),
-                    inertia=int(res["inertia"]))
+                    norm=res["norm_name"], train_ceiling=res["train_ceiling"], seed=synth.SEED,
+                    n_init=10, max_iter=300, table=os.path.relpath(a.table, HERE),
+                    device=meta.get("device"), inertia=res["inertia"])
         os.makedirs(os.path.dirname(a.spec), exist_ok=True)
         with open(a.spec, "w") as f:
             json.dump(spec, f, indent=1)

@@ -1,7 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times: the sweep set's largest problems, each run through the deployed path
-(k-means k = 8 on the measured table's training rows, decision tree B fitted
-on them, kt_gemm with config_id = -1), checked on sampled rows and columns of
+(k-means k = 8 on the measured table's training rows under the normalization
+that scores best there, decision tree B fitted on them, kt_gemm with
+config_id = -1), checked on sampled rows and columns of
 sampled batch items against the FP64 oracle (the tolerance is per element,
 so any subset is a valid check).
 
@@ -39,9 +40,11 @@ def _table(dtype_name):
 @pytest.fixture(scope="module")
 def deployed(gpu):
     """A fresh handle with the deployed selectors of bench.py: per dtype,
-    GPU k-means (k = 8, relative normalization, 10 restarts) on the training
-    rows of its table and decision tree B over the chosen kernels."""
+    GPU k-means (k = 8, 10 restarts, normalization chosen on the training
+    rows) on the training rows of its table and decision tree B over the
+    chosen kernels."""
     import paper_2008_13145_amd as kt
+    from paper_2008_13145_amd import tune
     _, torch = gpu
     h = kt.Handle(0)
     train, _ = synth.train_test_split()
@@ -54,8 +57,8 @@ def deployed(gpu):
             continue
         ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), T.shape[1], 8, 10)
         pws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-        chosen = h.prune(T[tr_rows], 8, norm=kt.NORM_RELATIVE, seed=synth.SEED, n_init=10,
-                         max_iter=300, workspace=pws, ws_bytes=ws_bytes)["chosen"]
+        chosen = tune.select_pruning(h, T[tr_rows], 8, synth.SEED, workspace=pws,
+                                     ws_bytes=ws_bytes)["chosen"]
         h.fit_selector(kt.SEL_DT_B, [problems[r] for r in tr_rows], T[tr_rows], chosen, dtype=dt)
         fitted[dt] = chosen
     torch.cuda.synchronize()
