@@ -169,9 +169,9 @@ struct LpTileLoader {
 // (op(A) stored K x M, or op(B) stored K x N), for an LDS layout with K
 // contiguous ([col][k]).  Each unit is 8 rows of K by a W-byte chunk of
 // columns (W = 4, 8 or 16, sized so the units spread over all threads): the
-// 8 chunks are loaded (coalesced along the columns), transposed in registers
-// with byte permutes, and written as one 8-deep K run per column (16 bytes
-// for BF16, 8 bytes for FP8).
+// 8 chunks are loaded, transposed in registers with byte permutes, and
+// written as one 8-deep K run per column (16 bytes for BF16, 8 bytes for
+// FP8), in a lane order chosen per unit width (see KFIRST).
 template <int EB, int KROWS, int COLS, int NT>
 struct LpTransposeLoader {
   typedef typename LpElem<EB>::T E;
@@ -180,7 +180,15 @@ struct LpTransposeLoader {
   static constexpr int WD = W / 4;                    // dwords per row chunk
   static constexpr int EPC = W / EB;                  // columns per unit
   static constexpr int CU = COLS / EPC;               // units across the columns
-  static constexpr int NU = (KROWS / 8) * CU;         // units in the tile
+  static constexpr int KU = KROWS / 8;                // units along K
+  static constexpr int NU = KU * CU;                  // units in the tile
+  // Lane -> unit order.  Units of 8 or more columns (16-byte chunks for
+  // BF16, 8- or 16-byte chunks for FP8) go K-first: neighbouring lanes take
+  // neighbouring K units of the same columns, so a store instruction fills
+  // consecutive runs of one LDS row, while each global load still covers
+  // row segments of 64 bytes or more.  Narrower units go column-first, where
+  // coalescing the global loads matters more than the LDS bank spread.
+  static constexpr bool KFIRST = EPC >= 8;
   static constexpr int UPT = (NU + NT - 1) / NT;
   static_assert(KROWS % 8 == 0 && COLS % EPC == 0, "tile must hold whole units");
   uint32_t v[UPT][8][WD];
@@ -195,7 +203,7 @@ struct LpTransposeLoader {
       for (int i = 0; i < UPT; ++i) {
         const int u = tid + i * NT;
         if (NU % NT != 0 && u >= NU) continue;
-        const int ku = u / CU, cu = u % CU;
+        const int ku = KFIRST ? u % KU : u / CU, cu = KFIRST ? u / KU : u % CU;
         const E* p0 = base + (k0 + ku * 8) * ld + col0 + cu * EPC;
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -210,7 +218,7 @@ struct LpTransposeLoader {
       for (int i = 0; i < UPT; ++i) {
         const int u = tid + i * NT;
         if (NU % NT != 0 && u >= NU) continue;
-        const int ku = u / CU, cu = u % CU;
+        const int ku = KFIRST ? u % KU : u / CU, cu = KFIRST ? u / KU : u % CU;
         const E* p0 = base + (k0 + ku * 8) * ld + col0 + cu * EPC;
 #pragma unroll
         for (int r = 0; r < 8; ++r) load_realigned<WD>(p0 + r * ld, v[i][r]);
@@ -221,7 +229,7 @@ struct LpTransposeLoader {
     for (int i = 0; i < UPT; ++i) {
       const int u = tid + i * NT;
       if (NU % NT != 0 && u >= NU) continue;
-      const int ku = u / CU, cu = u % CU;
+      const int ku = KFIRST ? u % KU : u / CU, cu = KFIRST ? u / KU : u % CU;
       const int64_t gc = col0 + cu * EPC;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -255,7 +263,7 @@ struct LpTransposeLoader {
     for (int i = 0; i < UPT; ++i) {
       const int u = tid + i * NT;
       if (NU % NT != 0 && u >= NU) continue;
-      const int ku = u / CU, cu = u % CU;
+      const int ku = KFIRST ? u % KU : u / CU, cu = KFIRST ? u / KU : u % CU;
 #pragma unroll
       for (int c = 0; c < EPC; ++c) {
         const int d = (c * EB) / 4;
