@@ -94,6 +94,25 @@ def measured_traffic(kernel_name):
     return None
 
 
+def deploy_info(chosen):
+    """Size of the pruned deploy build (section 4: only the k chosen kernels
+    ship) against the full build, and whether its recorded choice is the one
+    this run made."""
+    import json as _json
+    pkg = os.path.join(ROOT, "paper_2008_13145_amd")
+    full = os.path.join(pkg, "libkt.so")
+    dep = os.path.join(pkg, "libkt_deploy.so")
+    spec_path = os.path.join(pkg, "data", "deploy_f32.json")
+    out = {"full_library_bytes": os.path.getsize(full) if os.path.exists(full) else None,
+           "full_kernels": "164 FP32 + 68 BF16 + 68 FP8 configurations x 4 layouts"}
+    if os.path.exists(dep) and os.path.exists(spec_path):
+        spec = _json.load(open(spec_path))
+        out.update({"deploy_library_bytes": os.path.getsize(dep),
+                    "deploy_kernels": f"{len(spec['chosen'])} FP32 configurations x 4 layouts",
+                    "deploy_choice_matches_this_run": [int(c) for c in spec["chosen"]] == [int(c) for c in chosen]})
+    return out
+
+
 def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k, steps, stream):
     """BF16 / FP8 paths on the same 1200 problems: their own sweep tables,
     k-means pruning and decision tree B on the training shapes, a live pass of
@@ -390,6 +409,7 @@ def main(argv=None):
         },
         "table": {"path": os.path.relpath(table_path, ROOT), "device": meta.get("device"),
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
+        "deploy": deploy_info(chosen),
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
     if conv:

@@ -358,6 +358,9 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
   const E* __restrict__ Ag = static_cast<const E*>(args.A) + bz * args.sA;
   const E* __restrict__ Bg = static_cast<const E*>(args.B) + bz * args.sB;
   const int vecA = args.vecA, vecB = args.vecB;
+  // FP8 per-tensor scales: loaded before the K loop so their latency is hidden
+  float scale = args.alpha;
+  if (EB == 1) scale = args.alpha / (args.scaleA[0] * args.scaleB[0]);
 
   // A: TA == 0 -> k contiguous (direct 16-byte copy), TA == 1 -> m contiguous
   // (register transpose).  B: TB == 1 -> direct, TB == 0 -> transpose.
@@ -423,8 +426,6 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
     __syncthreads();
   }
 
-  float scale = args.alpha;
-  if (EB == 1) scale = args.alpha / (args.scaleA[0] * args.scaleB[0]);
   float* __restrict__ Cg = args.C + bz * args.sC;
   const float beta = args.beta;
 #pragma unroll
