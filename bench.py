@@ -94,7 +94,7 @@ def measured_traffic(kernel_name):
     return None
 
 
-def deploy_info(chosen):
+def deploy_info(chosen, n_configs):
     """Size of the pruned deploy build (section 4: only the k chosen kernels
     ship) against the full build, and whether its recorded choice is the one
     this run made."""
@@ -104,7 +104,7 @@ def deploy_info(chosen):
     dep = os.path.join(pkg, "libkt_deploy.so")
     spec_path = os.path.join(pkg, "data", "deploy_f32.json")
     out = {"full_library_bytes": os.path.getsize(full) if os.path.exists(full) else None,
-           "full_kernels": "164 FP32 + 68 BF16 + 68 FP8 configurations x 4 layouts"}
+           "full_kernels": "%d FP32 + %d BF16 + %d FP8 configurations x 4 layouts" % tuple(n_configs)}
     if os.path.exists(dep) and os.path.exists(spec_path):
         spec = _json.load(open(spec_path))
         out.update({"deploy_library_bytes": os.path.getsize(dep),
@@ -409,7 +409,7 @@ def main(argv=None):
         },
         "table": {"path": os.path.relpath(table_path, ROOT), "device": meta.get("device"),
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
-        "deploy": deploy_info(chosen),
+        "deploy": deploy_info(chosen, [h.num_configs(d) for d in (kt.F32, kt.BF16, kt.FP8E4M3)]),
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
     if conv:

@@ -68,12 +68,32 @@ def _lp_configs(k_tiles, elem_bytes):
     return out
 
 
+# 16x16 wave blocks (t = 2, the 16x16 MFMAs) for small and skinny problems,
+# appended after the larger blocks so the earlier ids keep their meaning; the
+# FP8 16x16 MFMA is 128 deep.
+SMALL_TILES = (16, 32, 64, 128, 256)
+BF16_SMALL_K_TILES = (32, 64)
+FP8_SMALL_K_TILES = (128,)
+
+
+def _lp_small_configs(k_tiles):
+    out = []
+    for bm in SMALL_TILES:
+        for bn in SMALL_TILES:
+            waves = (bm // 16) * (bn // 16)
+            if not 1 <= waves <= 16:
+                continue
+            for bk in k_tiles:
+                out.append((bm, bn, 2, bk))
+    return out
+
+
 def bf16_configs():
-    return _lp_configs(BF16_K_TILES, 2)
+    return _lp_configs(BF16_K_TILES, 2) + _lp_small_configs(BF16_SMALL_K_TILES)
 
 
 def fp8_configs():
-    return _lp_configs(FP8_K_TILES, 1)
+    return _lp_configs(FP8_K_TILES, 1) + _lp_small_configs(FP8_SMALL_K_TILES)
 
 
 DTYPES = (  # (name, config list, launcher template)

@@ -3,8 +3,9 @@
 // with s = 1 for BF16 and s = 1 / (scaleA * scaleB) for per-tensor-scaled FP8.
 //
 // Same configuration knobs as the FP32 family (work-group tile BM x BN, per
-// wave an (8T) x (8T) block, K depth BK per LDS stage), with T in {4, 8, 16}:
-// T = 4 is one 32x32 MFMA block per wave, T = 8 a 2x2 and T = 16 a 4x4 grid
+// wave an (8T) x (8T) block, K depth BK per LDS stage), with T in
+// {2, 4, 8, 16}: T = 2 is one 16x16 MFMA block per wave (16x16x32 BF16,
+// 16x16x128 FP8), T = 4 one 32x32 block, T = 8 a 2x2 and T = 16 a 4x4 grid
 // of them (the 4x4 grid keeps its 256 accumulators in AGPRs and halves the
 // LDS bytes read per MFMA against the 2x2 grid).
 // BF16 runs v_mfma_f32_32x32x16_bf16 (8 consecutive K values per lane, lane
@@ -37,9 +38,9 @@ typedef int i32x8a16 __attribute__((ext_vector_type(8), aligned(16)));
 template <int EB>   // element bytes: 2 = BF16, 1 = FP8 e4m3
 struct LpElem;
 template <>
-struct LpElem<2> { typedef uint16_t T; static constexpr int KSTEP = 16; };
+struct LpElem<2> { typedef uint16_t T; static constexpr int KSTEP = 16, KSTEP16 = 32; };
 template <>
-struct LpElem<1> { typedef uint8_t T; static constexpr int KSTEP = 64; };
+struct LpElem<1> { typedef uint8_t T; static constexpr int KSTEP = 64, KSTEP16 = 128; };
 
 // Operand alignment modes (GemmArgs::vecA / vecB for the low-precision
 // kernels): 2 = every row starts on a 4-byte boundary; 1 = only the operand's
@@ -293,6 +294,11 @@ struct LpTransposeLoader {
 template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
 struct GemmLpCfg {
   static constexpr int WT = 8 * T;
+  // T = 2 runs the 16x16 MFMAs (16x16x32 BF16, 16x16x128 FP8), larger T the
+  // 32x32 ones (32x32x16 BF16, 32x32x64 FP8).
+  static constexpr int MB = T == 2 ? 16 : 32;        // MFMA block edge
+  static constexpr int SUB = WT / MB;                // MFMA blocks per wave edge
+  static constexpr int KSTEP = T == 2 ? LpElem<EB>::KSTEP16 : LpElem<EB>::KSTEP;
   static constexpr int WAVES_N = BN / WT;
   static constexpr int WAVES = (BM / WT) * WAVES_N;
   static constexpr int NT = WAVES * 64;
@@ -301,10 +307,10 @@ struct GemmLpCfg {
   static constexpr int A_STAGE = BM * LDK;           // elements
   static constexpr int B_STAGE = BN * LDK;
   static constexpr int LDS_BYTES = 2 * (A_STAGE + B_STAGE) * EB;
-  static_assert(T == 4 || T == 8 || T == 16, "low-precision wave blocks are 32x32, 64x64 or 128x128");
+  static_assert(T == 2 || T == 4 || T == 8 || T == 16, "low-precision wave blocks of 16 to 128");
   static_assert(BM % WT == 0 && BN % WT == 0, "tile must hold whole wave blocks");
   static_assert(WAVES >= 1 && WAVES <= 16, "1..16 waves per work-group");
-  static_assert(BK % LpElem<EB>::KSTEP == 0, "BK multiple of the MFMA depth");
+  static_assert(BK % KSTEP == 0, "BK multiple of the MFMA depth");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
@@ -332,6 +338,14 @@ __device__ __forceinline__ void lp_mfma(const LpFrag<1>& a, const LpFrag<1>& b, 
   c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a.v, b.v, c, 0, 0, 0, 127, 0, 127);
 }
 
+__device__ __forceinline__ void lp_mfma(const LpFrag<2>& a, const LpFrag<2>& b, f32x4& c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void lp_mfma(const LpFrag<1>& a, const LpFrag<1>& b, f32x4& c) {
+  c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a.v, b.v, c, 0, 0, 0, 127, 0, 127);
+}
+
 // One BM x BN output tile (tile row tm, tile column tn) of batch item bz:
 // the whole K loop and the epilogue.  lds holds the two stages of both
 // operands; the caller synchronizes before reusing it for another tile.
@@ -343,7 +357,8 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
   constexpr int NT = Cfg::NT;
   constexpr int WT = Cfg::WT;
   constexpr int LDK = Cfg::LDK;
-  constexpr int SUB = T / 4;                 // 32x32 blocks per wave edge
+  constexpr int MB = Cfg::MB;                // MFMA block edge (16 or 32)
+  constexpr int SUB = Cfg::SUB;              // MFMA blocks per wave edge
   E* As = lds;                               // [2][BM][LDK]
   E* Bs = lds + 2 * Cfg::A_STAGE;            // [2][BN][LDK]
 
@@ -384,25 +399,25 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
     else                   lb.template store<LDK>(Bs + buf * Cfg::B_STAGE, tid);
   };
 
-  f32x16 acc[SUB][SUB];
+  typedef typename std::conditional<MB == 16, f32x4, f32x16>::type Acc;
+  constexpr int NACC = MB == 16 ? 4 : 16;
+  Acc acc[SUB][SUB];
 #pragma unroll
   for (int i = 0; i < SUB; ++i)
 #pragma unroll
     for (int j = 0; j < SUB; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+      for (int r = 0; r < NACC; ++r) acc[i][j][r] = 0.f;
 
-  constexpr int KSTEP = LpElem<EB>::KSTEP;
-  const int r32 = lane & 31, kh = (lane >> 5) * (KSTEP / 2);
+  // lane l feeds row l % MB of its block with K values from group l / MB
+  constexpr int KSTEP = Cfg::KSTEP;
+  const int rb = lane % MB, kh = (lane / MB) * (KSTEP * MB / 64);
   const int nk = (int)((K + BK - 1) / BK);
   if (nk > 0) {
     load_stage(0);
     store_stage(0);
     __syncthreads();
   }
-  // Fragments are double-buffered in registers: the reads for MFMA step
-  // s + 1 are issued before the MFMAs of step s, so LDS latency hides behind
-  // them even at one wave per SIMD.
   constexpr int NKK = BK / KSTEP;
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -414,8 +429,8 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
       LpFrag<EB> fa[SUB], fb[SUB];
 #pragma unroll
       for (int i = 0; i < SUB; ++i) {
-        fa[i].read(as + (wm0 + 32 * i + r32) * LDK + s * KSTEP + kh);
-        fb[i].read(bs + (wn0 + 32 * i + r32) * LDK + s * KSTEP + kh);
+        fa[i].read(as + (wm0 + MB * i + rb) * LDK + s * KSTEP + kh);
+        fb[i].read(bs + (wn0 + MB * i + rb) * LDK + s * KSTEP + kh);
       }
 #pragma unroll
       for (int i = 0; i < SUB; ++i)
@@ -433,9 +448,12 @@ __device__ __forceinline__ void lp_tile(const GemmArgs& args, int tm, int tn, in
 #pragma unroll
     for (int j = 0; j < SUB; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gi = m0 + wm0 + 32 * i + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int64_t gj = n0 + wn0 + 32 * j + r32;
+      for (int r = 0; r < NACC; ++r) {
+        // 32x32 blocks: row (r / 4) * 8 + (lane / 32) * 4 + r % 4; 16x16
+        // blocks: row (lane / 16) * 4 + r; the column is lane % MB
+        const int br = MB == 16 ? (lane >> 4) * 4 + r : (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int64_t gi = m0 + wm0 + MB * i + br;
+        const int64_t gj = n0 + wn0 + MB * j + rb;
         if (gi < M && gj < N) {
           float* p = Cg + gi * args.ldc + gj;
           float out = scale * acc[i][j][r];

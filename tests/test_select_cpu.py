@@ -121,5 +121,5 @@ def test_selectors_are_per_dtype(kt, tmp_path):
     with pytest.raises(kt.KtError):
         h2.select(64, 64, 64, dtype=kt.FP8E4M3)
     with pytest.raises(kt.KtError) as e:
-        h.fit_selector(0, shapes, T, [68], dtype=kt.BF16)     # BF16 has 68 configurations
+        h.fit_selector(0, shapes, T, [98], dtype=kt.BF16)     # BF16 has 98 configurations
     assert e.value.status == -1
