@@ -113,6 +113,69 @@ def deploy_info(chosen, n_configs):
     return out
 
 
+def grouped_section(kt, h, torch, synth, stream, reps=20):
+    """The persistent grouped BF16 GEMM on its workload (512 uneven GEMMs,
+    M, N, K log-uniform in 32..2048, A M x K, B K x N, FP32 out): the
+    library's autotuner picks (tile, schedule, order, work-groups per CU) on
+    the real group, then one hipGraph launch runs every member.  Reported
+    against the sum over members of each one's roofline time at peak BF16
+    MFMA rate and HBM bandwidth, and against one kt_gemm launch per member."""
+    shapes = synth.grouped_shapes()
+    a256 = lambda v: (v + 255) // 256 * 256
+    offs_a, offs_b, offs_c = [], [], []
+    na = nb = nc = 0
+    for (M, N, K) in shapes:
+        offs_a.append(na); na += a256(M * K * 2)
+        offs_b.append(nb); nb += a256(K * N * 2)
+        offs_c.append(nc); nc += a256(M * N * 4)
+    src = torch.empty((max(na, nb) + 3) // 2, dtype=torch.float32, device="cuda")
+    h.fill_uniform(src, src.numel(), synth.operand_seed(synth.SEED + 4, 0), stream=stream)
+    pa = torch.empty(na, dtype=torch.uint8, device="cuda")
+    pb = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    pc = torch.empty(nc, dtype=torch.uint8, device="cuda")
+    h.convert_bf16(src, na // 2, pa, stream=stream)
+    h.convert_bf16(src, nb // 2, pb, stream=stream)
+    del src
+    A = [pa.data_ptr() + o for o in offs_a]
+    B = [pb.data_ptr() + o for o in offs_b]
+    C = [pc.data_ptr() + o for o in offs_c]
+    wsb = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, best_ms, evals = h.autotune_grouped(shapes, A, B, C, ws, wsb, stream=stream)
+    tune_s = time.perf_counter() - t0
+    plan = h.grouped_plan(shapes, A, B, C, workspace=ws, ws_bytes=wsb, stream=stream)
+    for _ in range(3):
+        h.grouped_launch(plan, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        h.grouped_launch(plan, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for i, (M, N, K) in enumerate(shapes):
+        h.gemm_raw(kt.BF16, kt.shape(M, N, K), 1.0, A[i], K, 0, B[i], N, 0, 0.0, C[i], N, 0,
+                   config_id=best[0], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sep_ms = e0.elapsed_time(e1)
+    flops = sum(2.0 * m * n * k for (m, n, k) in shapes)
+    roof_ms = sum(max(2.0 * m * n * k / 2.5e15, (2.0 * (m * k + k * n) + 4.0 * m * n) / 8e12)
+                  for (m, n, k) in shapes) * 1e3
+    h.grouped_destroy(plan)
+    return {"members": len(shapes), "gflop": round(flops / 1e9, 2),
+            "config": list(h.get_config(best[0], kt.BF16)), "schedule": best[1], "order": best[2],
+            "wgs_per_cu": best[3], "autotune_evaluations": evals, "autotune_s": round(tune_s, 3),
+            "ms_per_launch": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+            "sum_member_roofline_ms": round(roof_ms, 4), "frac_of_sum_roofline": round(roof_ms / ms, 4),
+            "separate_launches_ms": round(sep_ms, 3), "speedup_vs_separate": round(sep_ms / ms, 2)}
+
+
 def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k, steps, stream):
     """BF16 / FP8 paths on the same 1200 problems: their own sweep tables,
     k-means pruning and decision tree B on the training shapes, a live pass of
@@ -419,6 +482,9 @@ def main(argv=None):
         if lp:
             out["lowp"] = lp
             _log(f"bench: low precision {json.dumps(lp)}")
+    if not a.no_lowp:
+        out["grouped_bf16"] = grouped_section(kt, h, torch, synth, stream)
+        _log(f"bench: grouped {json.dumps(out['grouped_bf16'])}")
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problems, a.cpu_budget_s)
     h.close()
