@@ -50,6 +50,28 @@ def test_config_space(kt):
     assert (64, 64, 4, 16) in cfgs
 
 
+def test_low_precision_config_spaces(kt):
+    """BF16 and FP8 spaces: the library's tables equal the generator's; the
+    MFMA depth divides every K tile (16 / 32 for BF16 32x32 / 16x16 blocks,
+    64 / 128 for FP8); every double-buffered stage fits the 160 KiB LDS; ids
+    0..67 are the 32x32-block configurations and the 16x16-block (t = 2)
+    ones follow; all are compiled for every layout."""
+    from paper_2008_13145_amd import codegen
+    h = kt.Handle(-1)
+    for dt, eb, gen, n, depth32, depth16 in ((kt.BF16, 2, codegen.bf16_configs, 98, 16, 32),
+                                             (kt.FP8E4M3, 1, codegen.fp8_configs, 83, 64, 128)):
+        cfgs = h.configs(dt)
+        assert cfgs == gen() and len(cfgs) == n
+        assert all(c[2] >= 4 for c in cfgs[:68]) and all(c[2] == 2 for c in cfgs[68:])
+        for (bm, bn, t, bk) in cfgs:
+            wt = 8 * t
+            assert bm % wt == 0 and bn % wt == 0 and 1 <= (bm // wt) * (bn // wt) <= 16
+            assert bk % (depth16 if t == 2 else depth32) == 0
+            assert 2 * (bm + bn) * (bk * eb + 16) <= 160 * 1024
+        assert len(set(cfgs)) == n
+        assert all(h.config_compiled(i, ta, tb, dtype=dt) for i in range(n) for ta, tb in synth.LAYOUTS)
+
+
 def test_host_handle_rejects_gpu_work(kt):
     h = kt.Handle(-1)
     s = kt.shape(8, 8, 8)
