@@ -355,6 +355,26 @@ def main(argv=None):
         evals[SEL_NAMES[kind]] = _geomean(ratios(te_rows, picks))
     conv = conv_section(kt, h, tune, tune.table_path("f32", "conv"), (0, 1, 2, 3),
                         (tr_shapes, T[tr_rows], chosen, mws, mws_bytes, stream))
+
+    # ---- the paper's comparison over the number of deployed kernels: for
+    # each k, pruning (normalization chosen on the training rows), Top-N and
+    # decision tree B, scored on the held-out rows (a separate handle, so the
+    # deployed selector above is untouched)
+    k_sweep = {}
+    hk = kt.Handle(0)
+    for kk in (4, 5, 6, 8, 15):
+        s_k = tune.select_pruning(hk, T[tr_rows], kk, synth.SEED, workspace=pws,
+                                  ws_bytes=ws_bytes, stream=stream)
+        tn_k = hk.prune_topn(T[tr_rows], kk, workspace=pws, ws_bytes=ws_bytes, stream=stream)
+        hk.fit_selector(kt.SEL_DT_B, tr_shapes, T[tr_rows], s_k["chosen"])
+        picks_k = [hk.select(*problems[r]) for r in te_rows]
+        k_sweep[str(kk)] = {
+            "normalization": s_k["norm_name"],
+            "kmeans_ceiling": round(100 * _geomean(t_best[te_rows] / T[te_rows][:, s_k["chosen"]].min(axis=1)), 2),
+            "topn_ceiling": round(100 * _geomean(t_best[te_rows] / T[te_rows][:, tn_k].min(axis=1)), 2),
+            "DT-B": round(100 * _geomean(ratios(te_rows, picks_k)), 2)}
+    hk.close()
+    _log(f"bench: k sweep {json.dumps(k_sweep)}")
     sel_kind = {v: kk for kk, v in SEL_NAMES.items()}[a.selector]
     h.fit_selector(sel_kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
                    workspace=mws, ws_bytes=mws_bytes, stream=stream)
@@ -473,6 +493,7 @@ def main(argv=None):
         "table": {"path": os.path.relpath(table_path, ROOT), "device": meta.get("device"),
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
         "deploy": deploy_info(chosen, [h.num_configs(d) for d in (kt.F32, kt.BF16, kt.FP8E4M3)]),
+        "k_sweep_pct_of_optimal_test": k_sweep,
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
     if conv:
