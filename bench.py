@@ -69,10 +69,22 @@ def cpu_baseline(problems, budget_s=15.0, seed=13145):
         n += 1
         if t_tot >= budget_s:
             break
-    return dict(value=round(flops / t_tot / 1e12, 6), unit="TFLOP/s", cores=og.max_threads(),
+    # the single 256^3 GEMM workload, on one core and on all of them
+    n_all = og.max_threads()
+    a = synth.uniform_operand(synth.operand_seed(synth.SEED + 1, 0), 256 * 256)
+    bb = synth.uniform_operand(synth.operand_seed(synth.SEED + 1, 1), 256 * 256)
+    single = {}
+    for nt in (1, n_all):
+        og.set_threads(nt)
+        t0 = time.perf_counter()
+        og.gemm(256, 256, 256, 1, 0, 0, 1.0, 0.0, a, 256, 65536, bb, 256, 65536)
+        single[f"{nt}_core" + ("s" if nt > 1 else "")] = round((time.perf_counter() - t0) * 1e3, 3)
+    og.set_threads(n_all)
+    return dict(value=round(flops / t_tot / 1e12, 6), unit="TFLOP/s", cores=n_all,
                 kind="oracle",
                 sample=f"{n} problems of the 1200-problem set (seeded order, each <= 2 GFLOP), "
-                       f"{flops / 1e9:.1f} GFLOP in {t_tot:.1f} s, FP64 triple loop")
+                       f"{flops / 1e9:.1f} GFLOP in {t_tot:.1f} s, FP64 triple loop",
+                single_gemm_256_ms=single)
 
 
 def measured_traffic(kernel_name):
@@ -92,6 +104,86 @@ def measured_traffic(kernel_name):
         if fields.get("kernel") == kernel_name and fields.get("kernel_source_sha256", "").split()[:1] == [sha]:
             return int(fields["traffic_bytes_per_launch"])
     return None
+
+
+def single_gemm_section(kt, h, torch, synth, stream, reps=200, warm=10):
+    """The single FP32 GEMM workload: M = N = K = 256, batch 1, NN, alpha 1,
+    beta 0, operands from seed SEED + 1, one fixed configuration (64x64 work
+    group, 4x4 thread tile, K-tile 16).  Mean over `reps` launches after
+    `warm` warm-ups, and the same launches replayed from one captured graph
+    (its parity is a GPU test; the oracle's time is in cpu_baseline)."""
+    M = N = K = 256
+    cid = h.configs().index((64, 64, 4, 16))
+    a = synth.uniform_operand(synth.operand_seed(synth.SEED + 1, 0), M * K).reshape(1, M, K)
+    b = synth.uniform_operand(synth.operand_seed(synth.SEED + 1, 1), K * N).reshape(1, K, N)
+    dA = torch.from_numpy(a).cuda()
+    dB = torch.from_numpy(b).cuda()
+    dC = torch.empty((1, M, N), dtype=torch.float32, device="cuda")
+    shp = kt.shape(M, N, K)
+
+    def launch(st):
+        h.gemm_raw(kt.F32, shp, 1.0, dA, K, M * K, dB, N, K * N, 0.0, dC, N, M * N,
+                   config_id=cid, stream=st)
+    for _ in range(warm):
+        launch(stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cs = torch.cuda.current_stream()
+        for _ in range(reps):
+            launch(cs)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us_graph = e0.elapsed_time(e1) * 1e3 / reps
+    F = 2.0 * M * N * K
+    t_roof_us = max(F / (FP32_PEAK_TFLOPS * 1e12), 4.0 * (M * K + K * N + M * N) / 8e12) * 1e6
+    return {"config": [64, 64, 4, 16], "us_per_launch": round(us, 3),
+            "tflops": round(F / (us * 1e-6) / 1e12, 3),
+            "us_per_launch_graph": round(us_graph, 3),
+            "tflops_graph": round(F / (us_graph * 1e-6) / 1e12, 3),
+            "pct_mfma_peak_graph": round(100 * F / (us_graph * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 2),
+            "t_roof_us": round(t_roof_us, 4), "frac_of_t_roof_graph": round(t_roof_us / us_graph, 4),
+            "work_groups": (M // 64) * (N // 64)}
+
+
+def repeatability(kt, h, torch, T, problems, plans, stream, n_rows=50, rounds=5, seed=13145):
+    """Re-time the best configuration of `n_rows` seeded rows `rounds` times
+    (operands resident, three launches per timing): coefficient of variation
+    per row."""
+    rng = np.random.default_rng(seed)
+    rows = sorted(int(r) for r in rng.choice(len(problems), n_rows, replace=False))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    cvs = []
+    for r in rows:
+        best = int(np.argmin(T[r]))
+        pl = plans[r]
+        ts = []
+        for _ in range(rounds):
+            e0.record(stream)
+            for _ in range(3):
+                h.gemm_raw(kt.F32, pl[0], 1.0, pl[1], pl[2], pl[3], pl[4], pl[5], pl[6], 0.0,
+                           pl[7], pl[8], pl[9], config_id=best, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts = np.array(ts)
+        cvs.append(float(ts.std() / ts.mean()))
+    cvs = np.array(cvs)
+    return {"rows": n_rows, "rounds": rounds, "cv_median": round(float(np.median(cvs)), 4),
+            "cv_p90": round(float(np.percentile(cvs, 90)), 4), "cv_max": round(float(cvs.max()), 4)}
 
 
 def deploy_info(chosen, n_configs):
@@ -339,6 +431,8 @@ def main(argv=None):
     # single best kernel over the training rows (no selector at all)
     single = int(np.argmax(np.exp(np.mean(np.log(t_best[tr_rows, None] / T[tr_rows]), axis=0))))
     evals["single_kernel"] = _geomean(ratios(te_rows, [single] * len(te_rows)))
+    frac09 = {"kmeans_ceiling": round(float(np.mean(ceil_te >= 0.9)), 4),
+              "topn_ceiling": round(float(np.mean(topn_te >= 0.9)), 4)}
 
     # ---- selectors fitted on the training rows
     tr_shapes = [problems[r] for r in tr_rows]
@@ -353,6 +447,7 @@ def main(argv=None):
         fit_ms[SEL_NAMES[kind]] = (time.perf_counter() - t0) * 1e3
         picks = [h.select(*problems[r]) for r in te_rows]
         evals[SEL_NAMES[kind]] = _geomean(ratios(te_rows, picks))
+        frac09[SEL_NAMES[kind]] = round(float(np.mean(ratios(te_rows, picks) >= 0.9)), 4)
     conv = conv_section(kt, h, tune, tune.table_path("f32", "conv"), (0, 1, 2, 3),
                         (tr_shapes, T[tr_rows], chosen, mws, mws_bytes, stream))
 
@@ -479,6 +574,7 @@ def main(argv=None):
         },
         "selector_pct_of_optimal_test": {kk: round(100 * v, 2) for kk, v in evals.items()},
         "selector_regret_test": {kk: round(1 - v, 4) for kk, v in evals.items()},
+        "selector_frac_ge_0.9_test": frac09,
         "select_us_per_call": round(select_us, 3),
         "prune_ms_gpu": round(prune_ms, 2),
         "fit_ms": {kk: round(v, 1) for kk, v in fit_ms.items()},
@@ -503,6 +599,10 @@ def main(argv=None):
         if lp:
             out["lowp"] = lp
             _log(f"bench: low precision {json.dumps(lp)}")
+    out["single_gemm_256"] = single_gemm_section(kt, h, torch, synth, stream)
+    out["repeatability"] = repeatability(kt, h, torch, T, problems, plans, stream)
+    _log(f"bench: single GEMM {json.dumps(out['single_gemm_256'])}; repeatability "
+         f"{json.dumps(out['repeatability'])}")
     if not a.no_lowp:
         out["grouped_bf16"] = grouped_section(kt, h, torch, synth, stream)
         _log(f"bench: grouped {json.dumps(out['grouped_bf16'])}")

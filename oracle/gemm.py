@@ -45,12 +45,19 @@ def _load():
                                                vp, i64, vp, i64, vp, vp]
         lib.kt_oracle_gemm_sampled.restype = None
         lib.kt_oracle_max_threads.restype = ci
+        lib.kt_oracle_set_threads.argtypes = [ci]
+        lib.kt_oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
 
 def max_threads() -> int:
     return int(_load().kt_oracle_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (timing only; results do not change)."""
+    _load().kt_oracle_set_threads(int(n))
 
 
 def _ptr(a):

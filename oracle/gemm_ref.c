@@ -106,3 +106,14 @@ int kt_oracle_max_threads(void) {
     return 1;
 #endif
 }
+
+/* Number of OpenMP threads later calls use (for timing the oracle on one
+ * core and on all of them); no effect on the arithmetic. */
+void kt_oracle_set_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
