@@ -468,8 +468,19 @@ def main(argv=None):
             "kmeans_ceiling": round(100 * _geomean(t_best[te_rows] / T[te_rows][:, s_k["chosen"]].min(axis=1)), 2),
             "topn_ceiling": round(100 * _geomean(t_best[te_rows] / T[te_rows][:, tn_k].min(axis=1)), 2),
             "DT-B": round(100 * _geomean(ratios(te_rows, picks_k)), 2)}
+    # ---- sparse-sampled tuning: prune from a random fraction of the
+    # training table's entries (the rest unmeasured), score on the held-out
+    # rows of the full table
+    sparse = {}
+    rng_s = np.random.default_rng(synth.SEED + 7)
+    for frac in (0.05, 0.1, 0.25, 0.5, 1.0):
+        T_s = T[tr_rows].copy()
+        T_s[rng_s.random(T_s.shape) >= frac] = -1
+        ch_s = hk.prune(T_s, k, norm=sel["norm"], seed=synth.SEED, n_init=10, max_iter=300,
+                        workspace=pws, ws_bytes=ws_bytes, stream=stream)["chosen"]
+        sparse[str(frac)] = round(100 * _geomean(t_best[te_rows] / T[te_rows][:, ch_s].min(axis=1)), 2)
     hk.close()
-    _log(f"bench: k sweep {json.dumps(k_sweep)}")
+    _log(f"bench: k sweep {json.dumps(k_sweep)}; sparse sampling {json.dumps(sparse)}")
     sel_kind = {v: kk for kk, v in SEL_NAMES.items()}[a.selector]
     h.fit_selector(sel_kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
                    workspace=mws, ws_bytes=mws_bytes, stream=stream)
@@ -590,6 +601,7 @@ def main(argv=None):
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
         "deploy": deploy_info(chosen, [h.num_configs(d) for d in (kt.F32, kt.BF16, kt.FP8E4M3)]),
         "k_sweep_pct_of_optimal_test": k_sweep,
+        "sparse_sampling_kmeans_ceiling_test": sparse,
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
     if conv:

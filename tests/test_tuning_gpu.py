@@ -66,6 +66,25 @@ def test_prune_kmeans_bitwise(gpu, k, norm, seed):
     assert got["chosen"] == okm.centroids_to_configs(ref["centroids"])
 
 
+@pytest.mark.parametrize("frac,norm", [(0.1, 0), (0.25, 2), (0.5, 1)])
+def test_prune_sparse_table_bitwise(gpu, frac, norm):
+    """Pruning from a sparsely measured table (only a random fraction of the
+    entries timed; the rest -1, which normalize to 0) still matches the
+    oracle bit for bit."""
+    kt_mod = __import__("paper_2008_13145_amd")
+    h, torch = gpu
+    rng = np.random.default_rng(int(frac * 100) + norm)
+    T = _planted_table(rng, 960, 164, 9)
+    T[rng.random(T.shape) >= frac] = -1
+    k, n_init, seed = 8, 10, 13145
+    ws_bytes = kt_mod.Handle.prune_workspace_bytes(960, 164, k, n_init)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    got = h.prune(T, k, norm=norm, seed=seed, n_init=n_init, workspace=ws, ws_bytes=ws_bytes)
+    ref = okm.kmeans(onz.normalize(T, norm), k, _draws(seed, n_init, k), 300)
+    assert got["inertia"] == ref["inertia"]
+    assert got["chosen"] == okm.centroids_to_configs(ref["centroids"])
+
+
 @pytest.mark.parametrize("n,d,k,max_iter", [(5, 3, 3, 300), (7, 4, 1, 300), (6, 6, 6, 300),
                                             (40, 10, 3, 0), (40, 10, 3, 1), (300, 20, 7, 2)])
 def test_prune_edge_cases(gpu, n, d, k, max_iter):
