@@ -46,7 +46,7 @@ def _geomean(x):
     return float(math.exp(np.mean(np.log(x))))
 
 
-def cpu_baseline(problems, budget_s=15.0, seed=13145):
+def cpu_baseline(problems, budget_s=15.0, seed=13145, tuning=None):
     """The FP64 CPU oracle (test infrastructure) timed on a bounded, seeded
     sample of the same problem set: problems are taken in a fixed seeded order
     (those up to 2 GFLOP each) until the time budget is spent."""
@@ -80,11 +80,27 @@ def cpu_baseline(problems, budget_s=15.0, seed=13145):
         og.gemm(256, 256, 256, 1, 0, 0, 1.0, 0.0, a, 256, 65536, bb, 256, 65536)
         single[f"{nt}_core" + ("s" if nt > 1 else "")] = round((time.perf_counter() - t0) * 1e3, 3)
     og.set_threads(n_all)
+    tuning_s = None
+    if tuning is not None:
+        # the tuning oracles on the deployed pruning's inputs (training rows
+        # of the measured table, its normalization, k): normalization plus
+        # 10-restart k-means, and decision tree B's fit
+        from oracle import cart, kmeans as okm, normalize as onorm
+        T_tr, shapes_tr, norm, k = tuning
+        t0 = time.perf_counter()
+        X = onorm.normalize(T_tr, norm)
+        km = okm.kmeans(X, k, okm.restart_draws(synth.SplitMix64, synth.SEED, 10, k), 300)
+        t1 = time.perf_counter()
+        ch = okm.centroids_to_configs(km["centroids"])
+        md, ml = cart.TREE_PARAMS["B"]
+        cart.fit(np.array(shapes_tr, dtype=np.int64), cart.labels_from_times(T_tr, ch), k, md, ml)
+        t2 = time.perf_counter()
+        tuning_s = {"prune_s": round(t1 - t0, 3), "fit_dt_b_s": round(t2 - t1, 4)}
     return dict(value=round(flops / t_tot / 1e12, 6), unit="TFLOP/s", cores=n_all,
                 kind="oracle",
                 sample=f"{n} problems of the 1200-problem set (seeded order, each <= 2 GFLOP), "
                        f"{flops / 1e9:.1f} GFLOP in {t_tot:.1f} s, FP64 triple loop",
-                single_gemm_256_ms=single)
+                single_gemm_256_ms=single, tuning=tuning_s)
 
 
 def measured_traffic(kernel_name):
@@ -184,6 +200,20 @@ def repeatability(kt, h, torch, T, problems, plans, stream, n_rows=50, rounds=5,
     cvs = np.array(cvs)
     return {"rows": n_rows, "rounds": rounds, "cv_median": round(float(np.median(cvs)), 4),
             "cv_p90": round(float(np.percentile(cvs, 90)), 4), "cv_max": round(float(cvs.max()), 4)}
+
+
+def gpu_state():
+    """Clocks, power and temperature of the GPU from rocm-smi (a child
+    process; None if it is unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showtemp", "--json"],
+                           capture_output=True, text=True, timeout=30)
+        card = next(iter(json.loads(r.stdout).values()))
+    except Exception:
+        return None
+    keep = ("sclk", "mclk", "fclk", "power", "temperature")
+    return {k: v for k, v in card.items() if any(w in k.lower() for w in keep)}
 
 
 def deploy_info(chosen, n_configs):
@@ -526,11 +556,13 @@ def main(argv=None):
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in problems] for _ in range(a.steps)]
     torch.cuda.synchronize()
+    state_before = gpu_state()
     t_start = time.perf_counter()
     for s in range(a.steps):
         step(evs[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    state_after = gpu_state()
     ms_per_step = wall * 1e3 / a.steps
     per_launch = np.array([[evs[s][i][0].elapsed_time(evs[s][i][1]) for i in range(n_prob)]
                            for s in range(a.steps)])          # ms
@@ -602,6 +634,7 @@ def main(argv=None):
         "deploy": deploy_info(chosen, [h.num_configs(d) for d in (kt.F32, kt.BF16, kt.FP8E4M3)]),
         "k_sweep_pct_of_optimal_test": k_sweep,
         "sparse_sampling_kmeans_ceiling_test": sparse,
+        "gpu_state": {"before": state_before, "after": state_after},
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
     if conv:
@@ -619,7 +652,8 @@ def main(argv=None):
         out["grouped_bf16"] = grouped_section(kt, h, torch, synth, stream)
         _log(f"bench: grouped {json.dumps(out['grouped_bf16'])}")
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(problems, a.cpu_budget_s)
+        out["cpu_baseline"] = cpu_baseline(problems, a.cpu_budget_s,
+                                           tuning=(T[tr_rows], tr_shapes, sel["norm"], k))
     h.close()
     print(json.dumps(out), flush=True)
     return 0
