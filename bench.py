@@ -509,8 +509,18 @@ def main(argv=None):
         ch_s = hk.prune(T_s, k, norm=sel["norm"], seed=synth.SEED, n_init=10, max_iter=300,
                         workspace=pws, ws_bytes=ws_bytes, stream=stream)["chosen"]
         sparse[str(frac)] = round(100 * _geomean(t_best[te_rows] / T[te_rows][:, ch_s].min(axis=1)), 2)
+    # ---- pruning in a reduced space: principal components of the normalized
+    # training table, then the same k-means and a member-mean representative
+    pca = {}
+    for dims in (8, 16, 32):
+        r_p = tune.pca_pruning(hk, T[tr_rows], k, synth.SEED, dims, sel["norm"], workspace=pws,
+                               ws_bytes=ws_bytes, stream=stream)
+        pca[str(dims)] = {"explained_variance": round(r_p["explained"], 4),
+                          "kmeans_ceiling": round(100 * _geomean(
+                              t_best[te_rows] / T[te_rows][:, r_p["chosen"]].min(axis=1)), 2)}
     hk.close()
-    _log(f"bench: k sweep {json.dumps(k_sweep)}; sparse sampling {json.dumps(sparse)}")
+    _log(f"bench: k sweep {json.dumps(k_sweep)}; sparse sampling {json.dumps(sparse)}; "
+         f"pca {json.dumps(pca)}")
     sel_kind = {v: kk for kk, v in SEL_NAMES.items()}[a.selector]
     h.fit_selector(sel_kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
                    workspace=mws, ws_bytes=mws_bytes, stream=stream)
@@ -634,6 +644,7 @@ def main(argv=None):
         "deploy": deploy_info(chosen, [h.num_configs(d) for d in (kt.F32, kt.BF16, kt.FP8E4M3)]),
         "k_sweep_pct_of_optimal_test": k_sweep,
         "sparse_sampling_kmeans_ceiling_test": sparse,
+        "pca_kmeans_ceiling_test": pca,
         "gpu_state": {"before": state_before, "after": state_after},
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")

@@ -213,6 +213,20 @@ kt_status kt_prune(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t 
                    void* workspace, size_t ws_bytes, void* stream,
                    int32_t* chosen, int64_t* inertia_out, int32_t* labels, int64_t* centroids);
 
+/* The same integer k-means as kt_prune (k-means++ from the SplitMix64
+ * stream seeded seed + restart, Lloyd, n_init restarts, lowest inertia wins)
+ * on arbitrary 16-bit vectors X (host array, n x d row-major), for pruning
+ * in a reduced space (section 4.1 clusters after a dimensionality
+ * reduction).  Writes labels[n] and, if centroids is not NULL,
+ * centroids[k * d] (rounded means) of the winning restart, and its inertia.
+ * Workspace sized by kt_prune_workspace_bytes(n, d, k, n_init).  Limits as
+ * kt_prune: n <= 4096, k <= 64, k * d <= 8192 (KT_EUNSUPPORTED beyond).
+ * Synchronizes `stream`. */
+kt_status kt_kmeans_u16(kt_handle h, const uint16_t* X, int32_t n, int32_t d, int32_t k,
+                        uint64_t seed, int32_t n_init, int32_t max_iter, void* workspace,
+                        size_t ws_bytes, void* stream, int32_t* labels, int64_t* centroids,
+                        int64_t* inertia_out);
+
 /* Top-N baseline of section 4.2: the k configurations that are best (largest
  * relative value, lowest index on ties) for the most rows, ties in the count
  * to the lower index.  time_ns and chosen are host arrays; the workspace is

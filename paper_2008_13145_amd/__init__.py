@@ -83,6 +83,8 @@ _SIGS = {
     "kt_prune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                          c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
     "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp, c_vp]),
+    "kt_kmeans_u16": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
+                              c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "kt_fit_selector": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp,
                                 c_i32, ctypes.POINTER(MlpOpts), c_vp, c_sz, c_vp]),
     "kt_select": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), ctypes.POINTER(c_i32)]),
@@ -328,6 +330,20 @@ class Handle:
                                          _ptr(workspace), int(ws_bytes), _stream(stream),
                                          chosen.ctypes.data))
         return chosen.tolist()
+
+    def kmeans_u16(self, X, k, seed=13145, n_init=10, max_iter=300, workspace=None, ws_bytes=0,
+                   stream=None):
+        """k-means on arbitrary 16-bit vectors (host array n x d)."""
+        Xa = np.ascontiguousarray(X, dtype=np.uint16)
+        n, d = Xa.shape
+        labels = np.zeros(n, dtype=np.int32)
+        cent = np.zeros((k, d), dtype=np.int64)
+        inertia = c_i64()
+        self._check(self.L.kt_kmeans_u16(self.h, Xa.ctypes.data, n, d, int(k), int(seed),
+                                         int(n_init), int(max_iter), _ptr(workspace),
+                                         int(ws_bytes), _stream(stream), labels.ctypes.data,
+                                         cent.ctypes.data, ctypes.byref(inertia)))
+        return {"labels": labels, "centroids": cent, "inertia": inertia.value}
 
     # ------------------------------------------------------------- select
     def fit_selector(self, kind, shapes, time_ns, chosen, mlp_steps=3000, mlp_lr=1e-3,

@@ -450,6 +450,57 @@ kt_status kt_prune(kt_handle hh, const int64_t* time_ns, int32_t n, int32_t d, i
   return KT_OK;
 }
 
+kt_status kt_kmeans_u16(kt_handle hh, const uint16_t* X, int32_t n, int32_t d, int32_t k,
+                        uint64_t seed, int32_t n_init, int32_t max_iter, void* workspace,
+                        size_t ws_bytes, void* stream, int32_t* labels, int64_t* centroids,
+                        int64_t* inertia_out) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!need_device(h)) return KT_EINVAL;
+  if (n < 1 || d < 1) return fail(h, KT_EINVAL, "need n >= 1 and d >= 1");
+  if (!X || !labels || !inertia_out) return fail(h, KT_EINVAL, "NULL argument");
+  if (k < 1 || k > n || k > 64) return fail(h, KT_EINVAL, "need 1 <= k <= min(n, 64)");
+  if (n_init < 1 || max_iter < 0) return fail(h, KT_EINVAL, "need n_init >= 1 and max_iter >= 0");
+  if (n > KM_MAX_ROWS || (int64_t)k * d > KM_MAX_KD)
+    return fail(h, KT_EUNSUPPORTED, "k-means limits: n <= 4096 and k * d <= 8192");
+  const PrunePlan p = prune_plan(n, d, k, n_init);
+  if (!workspace || ws_bytes < p.total) return fail(h, KT_EWORKSPACE, "k-means workspace too small");
+  char* ws = (char*)workspace;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(ws + p.off_X, X, (size_t)n * d * 2, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(h, e, "upload vectors");
+  const size_t lds = kmeans_lds_bytes(n, d, k);
+  e = hipFuncSetAttribute((const void*)kmeans_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds);
+  if (e != hipSuccess) return hip_fail(h, e, "kmeans LDS attribute");
+  hipLaunchKernelGGL(kmeans_kernel, dim3(n_init), dim3(KM_THREADS), lds, st,
+                     (const uint16_t*)(ws + p.off_X), n, d, k, seed, max_iter,
+                     (int64_t*)(ws + p.off_cent), (int32_t*)(ws + p.off_lab),
+                     (KmeansOut*)(ws + p.off_out));
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "kmeans launch");
+  // the restart with the lowest inertia (its per-coordinate picks are unused)
+  int32_t* d_chosen = (int32_t*)(ws + p.off_chosen);
+  hipLaunchKernelGGL(choose_kernel, dim3(1), dim3(64), 0, st, (const int64_t*)(ws + p.off_cent),
+                     (const KmeansOut*)(ws + p.off_out), n_init, k, d, d_chosen, d_chosen + k);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "choose launch");
+  int32_t br = 0;
+  e = hipMemcpyAsync(&br, d_chosen + k, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(h, e, "read best restart");
+  KmeansOut o;
+  e = hipMemcpy(&o, ws + p.off_out + br * sizeof(KmeansOut), sizeof o, hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(labels, ws + p.off_lab + (size_t)br * n * 4, (size_t)n * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && centroids)
+    e = hipMemcpy(centroids, ws + p.off_cent + (size_t)br * k * d * 8, (size_t)k * d * 8,
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "read k-means result");
+  *inertia_out = o.inertia;
+  return KT_OK;
+}
+
 kt_status kt_prune_topn(kt_handle hh, const int64_t* time_ns, int32_t n, int32_t d, int32_t k,
                         void* workspace, size_t ws_bytes, void* stream, int32_t* chosen) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);

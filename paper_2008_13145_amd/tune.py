@@ -68,6 +68,52 @@ def select_pruning(h, T_train, k, seed, n_init=10, max_iter=300, workspace=None,
             "inertia": best[3], "train_ceiling": scores}
 
 
+def clusters_to_configs(Xq, labels, k):
+    """Representative configuration per cluster (section 4.2) from its
+    members' rounded mean normalized row: the configuration with the largest
+    mean value not already taken (lowest index on ties), in cluster order."""
+    Xq = np.asarray(Xq, dtype=np.int64)
+    labels = np.asarray(labels)
+    chosen = []
+    for j in range(k):
+        rows = Xq[labels == j]
+        nj = len(rows)
+        m = (2 * rows.sum(axis=0) + nj) // (2 * nj) if nj else np.zeros(Xq.shape[1], np.int64)
+        order = sorted(range(Xq.shape[1]), key=lambda f: (-int(m[f]), f))
+        chosen.append(next(f for f in order if f not in chosen))
+    return chosen
+
+
+def pca_pruning(h, T_train, k, seed, dims, norm, n_init=10, max_iter=300, workspace=None,
+                ws_bytes=0, stream=None):
+    """k-means pruning in a reduced space (section 4.1: principal components
+    of the normalized table before clustering).  The table is normalized on
+    the GPU; the leading `dims` principal components of its rows (FP64 SVD
+    on the host) are quantized to 16 bits with one scale for all coordinates
+    (so Euclidean geometry is kept), clustered with the library's integer
+    k-means, and each cluster mapped back to a configuration by
+    clusters_to_configs.  Returns {"chosen", "inertia", "explained"}."""
+    import torch
+    T_train = np.ascontiguousarray(T_train, dtype=np.int64)
+    n, d = T_train.shape
+    dT = torch.from_numpy(T_train).cuda()
+    out = torch.zeros((n, d), dtype=torch.int16, device="cuda")
+    h.normalize(dT, n, d, norm, out, stream=stream)
+    torch.cuda.synchronize()
+    Xq = out.cpu().numpy().view(np.uint16).astype(np.int64)
+    Xf = Xq / 65535.0
+    Xc = Xf - Xf.mean(axis=0)
+    _, S, Vt = np.linalg.svd(Xc, full_matrices=False)
+    Z = Xc @ Vt[:dims].T
+    lo, span = float(Z.min()), float(Z.max() - Z.min())
+    U = np.zeros(Z.shape, np.uint16) if span == 0 else np.rint((Z - lo) / span * 65535).astype(np.uint16)
+    km = h.kmeans_u16(U, k, seed, n_init, max_iter, workspace=workspace, ws_bytes=ws_bytes,
+                      stream=stream)
+    var = S ** 2
+    return {"chosen": clusters_to_configs(Xq, km["labels"], k), "inertia": km["inertia"],
+            "explained": float(var[:dims].sum() / var.sum()) if var.sum() > 0 else 1.0}
+
+
 def load_table(path):
     """(time_ns int64 [P][C], problems int64 [P][6], configs int32 [C][4], meta dict)."""
     with np.load(path, allow_pickle=False) as z:

@@ -58,3 +58,17 @@ def test_select_pruning_ties_keep_the_earlier_normalization():
     res = tune.select_pruning(Same(), T, 2, 1)
     assert res["norm"] == 0 and res["chosen"] == [0, 1]
     assert len(set(res["train_ceiling"].values())) == 1
+
+
+def test_clusters_to_configs_matches_oracle_centroid_rule():
+    """The reduced-space pruning's cluster -> configuration step equals the
+    oracle's rounded-mean update followed by its centroid -> configuration
+    rule, applied in the original normalized space."""
+    rng = np.random.default_rng(11)
+    for trial in range(5):
+        n, d, k = 200, 30, 6
+        Xq = rng.integers(0, 65536, size=(n, d)).astype(np.int64)
+        labels = np.concatenate([np.arange(k), rng.integers(0, k, size=n - k)])
+        rng.shuffle(labels)
+        C = okm.update(Xq, labels, np.zeros(n, np.int64), np.zeros((k, d), np.int64))
+        assert tune.clusters_to_configs(Xq, labels, k) == okm.centroids_to_configs(C)

@@ -310,3 +310,53 @@ def test_exhaustive_selector_times_every_config_once_and_caches(gpu):
         assert e.value.status == -2
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("kind,n,d,k", [("random", 600, 16, 8), ("planted", 960, 12, 4),
+                                        ("random", 97, 3, 5)])
+def test_kmeans_u16_bitwise(gpu, kind, n, d, k):
+    """k-means on arbitrary 16-bit vectors (the reduced-space pruning's
+    clustering) equals the oracle bit for bit: labels, centroids, inertia."""
+    kt_mod = __import__("paper_2008_13145_amd")
+    h, torch = gpu
+    rng = np.random.default_rng(n + d + k)
+    if kind == "random":
+        X = rng.integers(0, 65536, size=(n, d)).astype(np.uint16)
+    else:
+        centres = rng.integers(5000, 60000, size=(k, d))
+        X = np.clip(centres[rng.integers(0, k, size=n)] + rng.integers(-2000, 2000, size=(n, d)),
+                    0, 65535).astype(np.uint16)
+    n_init, seed = 10, 13145
+    ws_bytes = kt_mod.Handle.prune_workspace_bytes(n, d, k, n_init)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    got = h.kmeans_u16(X, k, seed, n_init, 300, workspace=ws, ws_bytes=ws_bytes)
+    ref = okm.kmeans(X.astype(np.int64), k, _draws(seed, n_init, k), 300)
+    assert got["inertia"] == ref["inertia"]
+    assert np.array_equal(got["labels"], ref["labels"])
+    assert np.array_equal(got["centroids"], ref["centroids"])
+
+
+def test_pca_pruning_matches_oracle_steps(gpu):
+    """Pruning in a reduced space: the library's pipeline (GPU normalization,
+    host PCA and 16-bit quantization, GPU k-means, member-mean -> config)
+    gives the configurations the oracle's normalization, k-means and
+    centroid rule give on the same principal-component scores."""
+    kt_mod = __import__("paper_2008_13145_amd")
+    from paper_2008_13145_amd import tune
+    h, torch = gpu
+    rng = np.random.default_rng(21)
+    T = _planted_table(rng, 960, 164, 9)
+    k, dims, norm, seed = 8, 16, 2, 13145
+    ws_bytes = kt_mod.Handle.prune_workspace_bytes(960, dims, k, 10)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    got = tune.pca_pruning(h, T, k, seed, dims, norm, workspace=ws, ws_bytes=ws_bytes)
+    Xq = onz.normalize(T, norm).astype(np.int64)
+    Xf = Xq / 65535.0
+    Xc = Xf - Xf.mean(axis=0)
+    Z = Xc @ np.linalg.svd(Xc, full_matrices=False)[2][:dims].T
+    U = np.rint((Z - Z.min()) / (Z.max() - Z.min()) * 65535).astype(np.int64)
+    ref = okm.kmeans(U, k, _draws(seed, 10, k), 300)
+    C = okm.update(Xq, ref["labels"], np.zeros(len(Xq), np.int64), np.zeros((k, 164), np.int64))
+    assert got["inertia"] == ref["inertia"]
+    assert got["chosen"] == okm.centroids_to_configs(C)
+    assert 0 < got["explained"] <= 1
