@@ -174,6 +174,64 @@ def single_gemm_section(kt, h, torch, synth, stream, reps=200, warm=10):
             "work_groups": (M // 64) * (N // 64)}
 
 
+def splitk_section(kt, h, torch, T, problems, plans, chosen, stream, reps=5):
+    """Split-K on the rows whose exhaustive-best configuration leaves the chip
+    under-filled (fewer than 256 work-groups) with K >= 512: each row's
+    exhaustive-best plain launch against the best split-K launch over splits
+    {2, 4, 8, 16} x (that configuration and the k deployed ones), both timed
+    live on resident operands (mean of `reps` launches after one warm-up)."""
+    cfgs = h.configs()
+    rows = []
+    for r, (M, N, K, bt, ta, tb) in enumerate(problems):
+        bm, bn = cfgs[int(np.argmin(T[r]))][:2]
+        if K >= 512 and -(-M // bm) * -(-N // bn) * bt < 256:
+            rows.append(r)
+    if not rows:
+        return None
+    ws_bytes = max(kt.Handle.splitk_workspace_bytes(*problems[r][:4], 16) for r in rows)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    t_plain, t_split, best_pick = [], [], []
+    for r in rows:
+        pl = plans[r]
+        best = int(np.argmin(T[r]))
+        t_plain.append(timed(lambda: h.gemm_raw(kt.F32, pl[0], 1.0, pl[1], pl[2], pl[3], pl[4],
+                                                pl[5], pl[6], 0.0, pl[7], pl[8], pl[9],
+                                                config_id=best, stream=stream)))
+        cand = []
+        for cid in dict.fromkeys([best] + list(chosen)):
+            for sp in (2, 4, 8, 16):
+                us = timed(lambda: h.gemm_splitk_raw(kt.F32, pl[0], sp, 1.0, pl[1], pl[2], pl[3],
+                                                     pl[4], pl[5], pl[6], 0.0, pl[7], pl[8],
+                                                     pl[9], ws, ws_bytes, config_id=cid,
+                                                     stream=stream))
+                cand.append((us, sp, cid))
+        us, sp, cid = min(cand)
+        t_split.append(us)
+        best_pick.append((sp, cid))
+    t_plain, t_split = np.array(t_plain), np.array(t_split)
+    speed = t_plain / np.minimum(t_plain, t_split)
+    i = int(np.argmax(t_plain / t_split))
+    return {"rows": len(rows), "rows_where_split_k_wins": int((t_split < t_plain).sum()),
+            "geomean_speedup_best_of_both": round(_geomean(speed), 4),
+            "max_speedup": round(float(t_plain[i] / t_split[i]), 3),
+            "max_speedup_problem": list(problems[rows[i]]),
+            "max_speedup_pick": {"splits": best_pick[i][0], "config": list(cfgs[best_pick[i][1]])},
+            "us_plain_sum": round(float(t_plain.sum()), 1),
+            "us_best_of_both_sum": round(float(np.minimum(t_plain, t_split).sum()), 1)}
+
+
 def repeatability(kt, h, torch, T, problems, plans, stream, n_rows=50, rounds=5, seed=13145):
     """Re-time the best configuration of `n_rows` seeded rows `rounds` times
     (operands resident, three launches per timing): coefficient of variation
@@ -657,6 +715,8 @@ def main(argv=None):
             _log(f"bench: low precision {json.dumps(lp)}")
     out["single_gemm_256"] = single_gemm_section(kt, h, torch, synth, stream)
     out["repeatability"] = repeatability(kt, h, torch, T, problems, plans, stream)
+    out["split_k"] = splitk_section(kt, h, torch, T, problems, plans, chosen, stream)
+    _log(f"bench: split-K {json.dumps(out['split_k'])}")
     _log(f"bench: single GEMM {json.dumps(out['single_gemm_256'])}; repeatability "
          f"{json.dumps(out['repeatability'])}")
     if not a.no_lowp:

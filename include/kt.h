@@ -137,6 +137,30 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
                   const float* scaleA, const float* scaleB,
                   int32_t config_id, void* stream);
 
+/* Split-K form of kt_gemm for deep products with few output tiles, the
+ * tall-skinny / very deep K case that section 3 names as its kernel's worst
+ * (fix: divide the K range among work-groups).  The K range is cut into
+ * S = ceil(K / kc) slices of depth kc = ceil(K / splits) rounded up to a
+ * multiple of 64 (so S <= splits; the last slice may be shallower); slice q
+ * is computed with configuration config_id (-1: the selector, asked for the
+ * shape M, N, kc with batch * S items) into FP32 partial planes in the
+ * workspace (device, dense, [S][batch][M][N]), and one reduction pass writes
+ * C = alpha * (sum of the planes in slice order) + beta * C (C not read when
+ * beta == 0).  Arguments and layouts as kt_gemm; 1 <= splits <= 64.  When
+ * S == 1 (splits == 1 or K <= 64) this is exactly kt_gemm and needs no
+ * workspace.  *used_splits (host, may be NULL) receives S.  The workspace
+ * must stay untouched until the work on `stream` has finished.
+ * KT_EWORKSPACE if it is smaller than kt_gemm_splitk_workspace_bytes. */
+kt_status kt_gemm_splitk(kt_handle h, kt_dtype in_dtype, const kt_shape* s, int32_t splits,
+                         float alpha, const void* A, int64_t lda, int64_t strideA,
+                         const void* B, int64_t ldb, int64_t strideB, float beta, float* C,
+                         int64_t ldc, int64_t strideC, const float* scaleA, const float* scaleB,
+                         int32_t config_id, void* workspace, size_t ws_bytes, void* stream,
+                         int32_t* used_splits);
+/* Workspace bytes of kt_gemm_splitk: splits * batch * M * N floats, rounded
+ * up to 256 bytes (0 for splits == 1).  Host only. */
+kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size_t* bytes);
+
 /* Fill dst[i] (device, n floats) with the seeded operand stream
  * x(seed, offset + i) = (splitmix64(seed XOR (offset + i)) >> 40) * 2^-23 - 1,
  * values in [-1, 1) exact in FP32. */

@@ -72,6 +72,10 @@ _SIGS = {
     "kt_config_compiled": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_i32)]),
     "kt_gemm": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_f32, c_vp, c_i64, c_i64, c_vp, c_i64,
                         c_i64, c_f32, c_vp, c_i64, c_i64, c_vp, c_vp, c_i32, c_vp]),
+    "kt_gemm_splitk": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_f32, c_vp, c_i64,
+                               c_i64, c_vp, c_i64, c_i64, c_f32, c_vp, c_i64, c_i64, c_vp, c_vp,
+                               c_i32, c_vp, c_sz, c_vp, ctypes.POINTER(c_i32)]),
+    "kt_gemm_splitk_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
     "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
     "kt_convert_bf16": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "kt_quantize_fp8": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
@@ -229,12 +233,9 @@ class Handle:
             self._check(st)
         return st
 
-    def gemm(self, A, B, C, transA=0, transB=0, alpha=1.0, beta=0.0, config_id=-1, dtype=F32,
-             scaleA=None, scaleB=None, stream=None):
-        """Batched GEMM on 3-D (or 2-D) row-major device tensors: A is
-        (batch, M, K) or (batch, K, M) when transA, B is (batch, K, N) or
-        (batch, N, K), C is (batch, M, N).  Leading dimensions and batch
-        strides are read from the tensors' strides."""
+    @staticmethod
+    def _operands(A, B, C, transA, transB):
+        """(shape, lda, sA, ldb, sB, ldc, sC) of row-major device tensors."""
         def dims(t):
             # strides of size-1 dimensions carry no information and are ignored
             if t.dim() == 2:
@@ -251,8 +252,47 @@ class Handle:
         K = ra if transA else ca
         if (ca if transA else ra) != M or (rb if transB else cb) != N or (cb if transB else rb) != K:
             raise ValueError("inconsistent operand shapes")
-        return self.gemm_raw(dtype, shape(M, N, K, bc, transA, transB), alpha, A, lda, sA, B, ldb,
-                             sB, beta, C, ldc, sC, scaleA, scaleB, config_id, stream)
+        return shape(M, N, K, bc, transA, transB), lda, sA, ldb, sB, ldc, sC
+
+    def gemm(self, A, B, C, transA=0, transB=0, alpha=1.0, beta=0.0, config_id=-1, dtype=F32,
+             scaleA=None, scaleB=None, stream=None):
+        """Batched GEMM on 3-D (or 2-D) row-major device tensors: A is
+        (batch, M, K) or (batch, K, M) when transA, B is (batch, K, N) or
+        (batch, N, K), C is (batch, M, N).  Leading dimensions and batch
+        strides are read from the tensors' strides."""
+        shp, lda, sA, ldb, sB, ldc, sC = self._operands(A, B, C, transA, transB)
+        return self.gemm_raw(dtype, shp, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
+                             scaleA, scaleB, config_id, stream)
+
+    @staticmethod
+    def splitk_workspace_bytes(M, N, K, batch, splits) -> int:
+        b = c_sz()
+        st = lib().kt_gemm_splitk_workspace_bytes(ctypes.byref(shape(M, N, K, batch)), int(splits),
+                                                  ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "split-K workspace query")
+        return b.value
+
+    def gemm_splitk(self, A, B, C, splits, workspace, ws_bytes, transA=0, transB=0, alpha=1.0,
+                    beta=0.0, config_id=-1, dtype=F32, scaleA=None, scaleB=None, stream=None):
+        """Split-K GEMM on tensors laid out as for gemm(); returns the number
+        of K slices used."""
+        shp, lda, sA, ldb, sB, ldc, sC = self._operands(A, B, C, transA, transB)
+        return self.gemm_splitk_raw(dtype, shp, splits, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                                    ldc, sC, workspace, ws_bytes, scaleA, scaleB, config_id,
+                                    stream)
+
+    def gemm_splitk_raw(self, dtype, shp: Shape, splits, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                        ldc, sC, workspace, ws_bytes, scaleA=None, scaleB=None, config_id=-1,
+                        stream=None):
+        used = c_i32(0)
+        self._check(self.L.kt_gemm_splitk(self.h, dtype, ctypes.byref(shp), int(splits),
+                                          float(alpha), _ptr(A), int(lda), int(sA), _ptr(B),
+                                          int(ldb), int(sB), float(beta), _ptr(C), int(ldc),
+                                          int(sC), _ptr(scaleA), _ptr(scaleB), int(config_id),
+                                          _ptr(workspace), int(ws_bytes), _stream(stream),
+                                          ctypes.byref(used)))
+        return used.value
 
     def fill_uniform(self, dst, n, seed, offset=0, stream=None):
         self._check(self.L.kt_fill_uniform(self.h, _ptr(dst), int(n), int(seed) & (2 ** 64 - 1),

@@ -98,3 +98,17 @@ def test_sweep_workspace_query(kt):
     # A 2*100*300 + B 2*300*200 + C 2*100*200 floats, each region 256-aligned, plus scale slot
     assert n >= 4 * (60000 + 120000 + 40000)
     assert n % 256 == 0
+
+
+def test_splitk_workspace_query_and_host_handle(kt):
+    # splits * batch * M * N floats, 256-aligned; one slice needs none
+    assert kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, 8) == -(-8 * 3 * 100 * 70 * 4 // 256) * 256
+    assert kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, 1) == 0
+    for bad in (0, 65, -2):
+        with pytest.raises(kt.KtError):
+            kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, bad)
+    h = kt.Handle(-1)
+    s = kt.shape(8, 8, 512)
+    st = h.L.kt_gemm_splitk(h.h, 0, ctypes.byref(s), 4, 1.0, None, 512, 0, None, 8, 0, 0.0, None, 8,
+                            0, None, None, 0, None, 0, None, None)
+    assert st == -1 and "device" in h.L.kt_last_error(h.h).decode()
