@@ -232,6 +232,128 @@ def splitk_section(kt, h, torch, T, problems, plans, chosen, stream, reps=5):
             "us_best_of_both_sum": round(float(np.minimum(t_plain, t_split).sum()), 1)}
 
 
+# VGG16 (configuration D of Simonyan and Zisserman): 3x3 convolutions with
+# stride 1 and padding 1 (output channels listed), "M" = 2x2 max pool, then
+# three fully connected layers.
+VGG16_CONV = [64, 64, "M", 128, 128, "M", 256, 256, 256, "M", 512, 512, 512, "M",
+              512, 512, 512, "M"]
+VGG16_FC = [(7 * 7 * 512, 4096), (4096, 4096), (4096, 1000)]
+
+
+def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
+    """Single-image VGG16 inference (224x224x3, random weights scaled by
+    1/sqrt(fan-in), FP32, NHWC): 13 3x3 convolutions with ReLU, 5 max pools,
+    3 fully connected layers run as 1x1 convolutions of a 1x1 image.  Every
+    GEMM's configuration comes from the deployed selector (config -1); the
+    3x3 convolutions are timed with im2col and with Winograd F(2x2,3x3), and
+    each layer's GEMM is also run with every configuration to give the
+    exhaustive-best time of the same lowering."""
+    layers = []   # (kind, conv_shape)
+    H, C = 224, 3
+    for v in VGG16_CONV:
+        if v == "M":
+            layers.append(("pool", (H, C)))
+            H //= 2
+        else:
+            layers.append(("conv", kt.conv_shape(1, H, H, C, v)))
+            C = v
+    for (fi, fo) in VGG16_FC:
+        layers.append(("fc", kt.conv_shape(1, 1, 1, fi, fo, 1, 1, 1, 0)))
+    convs = [cs for kind, cs in layers if kind != "pool"]
+    ws_bytes = max(kt.Handle.conv_workspace_bytes(cs, al) for cs in convs
+                   for al in ((kt.CONV_IM2COL, kt.CONV_WINOGRAD) if cs.R == 3 else (kt.CONV_IM2COL,)))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    weights, biases = [], []
+    for i, cs in enumerate(convs):
+        n_w = cs.R * cs.S * cs.Cin * cs.Cout
+        wt = torch.empty(n_w, dtype=torch.float32, device="cuda")
+        h.fill_uniform(wt, n_w, synth.operand_seed(synth.SEED + 100 + i, 1), stream=stream)
+        wt.mul_(1.0 / math.sqrt(cs.R * cs.S * cs.Cin))
+        bt = torch.empty(cs.Cout, dtype=torch.float32, device="cuda")
+        h.fill_uniform(bt, cs.Cout, synth.operand_seed(synth.SEED + 100 + i, 2), stream=stream)
+        weights.append(wt)
+        biases.append(bt)
+    x0 = torch.empty(224 * 224 * 3, dtype=torch.float32, device="cuda")
+    h.fill_uniform(x0, x0.numel(), synth.operand_seed(synth.SEED + 99, 0), stream=stream)
+    buf = [torch.empty(224 * 224 * 64, dtype=torch.float32, device="cuda") for _ in range(2)]
+    flops = sum(2.0 * cs.H * cs.W * cs.Cout * cs.R * cs.S * cs.Cin for cs in convs)
+
+    def forward(algo_of, cfg_of=lambda li: -1):
+        src, li = x0, 0
+        for kind, cs in layers:
+            dst = buf[0] if src is not buf[0] else buf[1]
+            if kind == "pool":
+                Hp, Cp = cs
+                h.maxpool2x2(src, 1, Hp, Hp, Cp, dst, stream=stream)
+            else:
+                h.conv2d(algo_of(li, cs), cs, src, weights[li], biases[li], kind == "conv" or li < len(convs) - 1,
+                         dst, ws, ws_bytes, config_id=cfg_of(li), stream=stream)
+                li += 1
+            src = dst
+        return src
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        fn()
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    def wino_if_3x3(li, cs):
+        return kt.CONV_WINOGRAD if cs.R == 3 else kt.CONV_IM2COL
+
+    # per-layer times: selector pick and exhaustive best, for each lowering
+    per = []
+    src = x0
+    cfgs = h.configs()
+    li = 0
+    for kind, cs in layers:
+        if kind == "pool":
+            continue
+        xin = torch.empty(cs.H * cs.W * cs.Cin, dtype=torch.float32, device="cuda")
+        h.fill_uniform(xin, xin.numel(), synth.operand_seed(synth.SEED + 200 + li, 0), stream=stream)
+        out = torch.empty(cs.H * cs.W * cs.Cout, dtype=torch.float32, device="cuda")
+        row = {"layer": li, "H": cs.H, "Cin": cs.Cin, "Cout": cs.Cout}
+        for algo, name in ((kt.CONV_IM2COL, "im2col"), (kt.CONV_WINOGRAD, "winograd")):
+            if algo == kt.CONV_WINOGRAD and cs.R != 3:
+                continue
+            sel = timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out, ws,
+                                         ws_bytes, stream=stream), reps)
+            best = min((timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out, ws,
+                                               ws_bytes, config_id=c, stream=stream), cfg_reps), c)
+                       for c in range(len(cfgs)))
+            row[name] = {"ms_selected": round(sel, 4), "ms_exhaustive": round(best[0], 4),
+                         "exhaustive_config": list(cfgs[best[1]]),
+                         "gemm": list(kt.Handle.conv_gemm_shape(cs, algo)[:4])}
+        per.append(row)
+        li += 1
+    best_algo = {r["layer"]: (kt.CONV_WINOGRAD if "winograd" in r and
+                              r["winograd"]["ms_selected"] < r["im2col"]["ms_selected"]
+                              else kt.CONV_IM2COL) for r in per}
+    ex_cfg = {}
+    for r in per:
+        nm = "winograd" if best_algo[r["layer"]] == kt.CONV_WINOGRAD else "im2col"
+        ex_cfg[r["layer"]] = cfgs.index(tuple(r[nm]["exhaustive_config"]))
+    ms = {
+        "im2col_selected": timed(lambda: forward(lambda li, cs: kt.CONV_IM2COL), reps),
+        "winograd_selected": timed(lambda: forward(wino_if_3x3), reps),
+        "best_lowering_selected": timed(lambda: forward(lambda li, cs: best_algo[li]), reps),
+        "best_lowering_exhaustive": timed(lambda: forward(lambda li, cs: best_algo[li],
+                                                          lambda li: ex_cfg[li]), reps),
+    }
+    torch.cuda.synchronize()
+    return {"ms_per_inference": {kk: round(v, 4) for kk, v in ms.items()},
+            "gflop_direct": round(flops / 1e9, 2),
+            "tflops_effective_best_lowering_selected": round(flops / (ms["best_lowering_selected"] * 1e-3) / 1e12, 2),
+            "selected_pct_of_exhaustive": round(100 * ms["best_lowering_exhaustive"] / ms["best_lowering_selected"], 2),
+            "layers": per}
+
+
 def repeatability(kt, h, torch, T, problems, plans, stream, n_rows=50, rounds=5, seed=13145):
     """Re-time the best configuration of `n_rows` seeded rows `rounds` times
     (operands resident, three launches per timing): coefficient of variation
@@ -717,6 +839,9 @@ def main(argv=None):
     out["repeatability"] = repeatability(kt, h, torch, T, problems, plans, stream)
     out["split_k"] = splitk_section(kt, h, torch, T, problems, plans, chosen, stream)
     _log(f"bench: split-K {json.dumps(out['split_k'])}")
+    out["vgg16"] = vgg16_section(kt, h, torch, synth, stream)
+    _log(f"bench: VGG16 {json.dumps(out['vgg16']['ms_per_inference'])}, "
+         f"{out['vgg16']['selected_pct_of_exhaustive']} % of exhaustive")
     _log(f"bench: single GEMM {json.dumps(out['single_gemm_256'])}; repeatability "
          f"{json.dumps(out['repeatability'])}")
     if not a.no_lowp:

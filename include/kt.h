@@ -161,6 +161,47 @@ kt_status kt_gemm_splitk(kt_handle h, kt_dtype in_dtype, const kt_shape* s, int3
  * up to 256 bytes (0 for splits == 1).  Host only. */
 kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size_t* bytes);
 
+/* ------------------------------------------------------------ convolution */
+
+/* Convolution layers through the selected GEMMs (section 6 runs VGG16, whose
+ * convolutions and fully connected layers are matrix multiplications).
+ * Activations are NHWC FP32 (n, H, W, C), filters (R, S, Cin, Cout) FP32,
+ * zero padding `pad` on every side, output (n, Ho, Wo, Cout) with
+ * Ho = (H + 2 pad - R) / stride + 1 (Wo likewise):
+ *   y[b,i,j,o] = act(bias[o] + sum_{r,s,c} x[b, i*stride-pad+r, j*stride-pad+s, c] * w[r,s,c,o]).
+ * KT_CONV_IM2COL: any R, S, stride; the rows of the (n Ho Wo) x (R S Cin)
+ * patch matrix are built in the workspace and multiplied by the filter.
+ * KT_CONV_WINOGRAD: F(2x2, 3x3) (Lavin and Gray): R = S = 3, stride 1
+ * (KT_EUNSUPPORTED otherwise); input and filter transforms in the workspace,
+ * 16 GEMMs of T x Cin by Cin x Cout in one batched launch (T = n ceil(Ho/2)
+ * ceil(Wo/2) tiles), output transform with bias and activation fused. */
+typedef enum { KT_CONV_IM2COL = 0, KT_CONV_WINOGRAD = 1 } kt_conv_algo;
+
+typedef struct {
+  int64_t n, H, W, Cin, Cout;
+  int32_t R, S, stride, pad;
+} kt_conv_shape;
+
+/* The GEMM a convolution runs (what the selector is asked about):
+ * im2col {n Ho Wo, Cout, R S Cin, batch 1}, Winograd {T, Cout, Cin, batch 16},
+ * both non-transposed.  Host only. */
+kt_status kt_conv2d_gemm_shape(const kt_conv_shape* c, kt_conv_algo algo, kt_shape* out);
+/* Device workspace of kt_conv2d (im2col: the patch matrix; Winograd: the
+ * transformed input, filter and the 16 products, each 256-byte aligned). */
+kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, size_t* bytes);
+/* y = conv(x, w) + bias, then ReLU when relu != 0.  x, w, bias (NULL = no
+ * bias; Cout floats), y and workspace are device pointers; y must not alias
+ * x or the workspace.  config_id: FP32 configuration of the GEMM, -1 = the
+ * fitted selector on kt_conv2d_gemm_shape.  Empty n, Ho or Wo is a no-op.
+ * Asynchronous on `stream`. */
+kt_status kt_conv2d(kt_handle h, kt_conv_algo algo, const kt_conv_shape* c, const float* x,
+                    const float* w, const float* bias, int32_t relu, float* y, int32_t config_id,
+                    void* workspace, size_t ws_bytes, void* stream);
+/* 2x2 max pooling with stride 2 on NHWC FP32 (device): y is
+ * (n, H/2, W/2, C); an odd trailing row or column is dropped. */
+kt_status kt_maxpool2x2(kt_handle h, const float* x, int64_t n, int64_t H, int64_t W, int64_t C,
+                        float* y, void* stream);
+
 /* Fill dst[i] (device, n floats) with the seeded operand stream
  * x(seed, offset + i) = (splitmix64(seed XOR (offset + i)) >> 40) * 2^-23 - 1,
  * values in [-1, 1) exact in FP32. */

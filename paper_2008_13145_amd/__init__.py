@@ -55,6 +55,18 @@ class GroupedOpts(ctypes.Structure):
                 ("visits", c_vp)]
 
 
+class ConvShape(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("H", c_i64), ("W", c_i64), ("Cin", c_i64), ("Cout", c_i64),
+                ("R", c_i32), ("S", c_i32), ("stride", c_i32), ("pad", c_i32)]
+
+
+CONV_IM2COL, CONV_WINOGRAD = 0, 1
+
+
+def conv_shape(n, H, W, Cin, Cout, R=3, S=3, stride=1, pad=1) -> ConvShape:
+    return ConvShape(n, H, W, Cin, Cout, R, S, stride, pad)
+
+
 class KtError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -76,6 +88,11 @@ _SIGS = {
                                c_i64, c_vp, c_i64, c_i64, c_f32, c_vp, c_i64, c_i64, c_vp, c_vp,
                                c_i32, c_vp, c_sz, c_vp, ctypes.POINTER(c_i32)]),
     "kt_gemm_splitk_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
+    "kt_conv2d_gemm_shape": (c_i32, [ctypes.POINTER(ConvShape), c_i32, ctypes.POINTER(Shape)]),
+    "kt_conv2d_workspace_bytes": (c_i32, [ctypes.POINTER(ConvShape), c_i32, ctypes.POINTER(c_sz)]),
+    "kt_conv2d": (c_i32, [c_vp, c_i32, ctypes.POINTER(ConvShape), c_vp, c_vp, c_vp, c_i32, c_vp,
+                          c_i32, c_vp, c_sz, c_vp]),
+    "kt_maxpool2x2": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
     "kt_convert_bf16": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "kt_quantize_fp8": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
@@ -293,6 +310,33 @@ class Handle:
                                           _ptr(workspace), int(ws_bytes), _stream(stream),
                                           ctypes.byref(used)))
         return used.value
+
+    # -------------------------------------------------------- convolution
+    @staticmethod
+    def conv_gemm_shape(c: ConvShape, algo) -> tuple:
+        out = Shape()
+        st = lib().kt_conv2d_gemm_shape(ctypes.byref(c), int(algo), ctypes.byref(out))
+        if st != 0:
+            raise KtError(st, "conv GEMM shape query")
+        return (out.M, out.N, out.K, out.batch, out.transA, out.transB)
+
+    @staticmethod
+    def conv_workspace_bytes(c: ConvShape, algo) -> int:
+        b = c_sz()
+        st = lib().kt_conv2d_workspace_bytes(ctypes.byref(c), int(algo), ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "conv workspace query")
+        return b.value
+
+    def conv2d(self, algo, c: ConvShape, x, w, bias, relu, y, workspace, ws_bytes, config_id=-1,
+               stream=None):
+        self._check(self.L.kt_conv2d(self.h, int(algo), ctypes.byref(c), _ptr(x), _ptr(w),
+                                     _ptr(bias), int(bool(relu)), _ptr(y), int(config_id),
+                                     _ptr(workspace), int(ws_bytes), _stream(stream)))
+
+    def maxpool2x2(self, x, n, H, W, C, y, stream=None):
+        self._check(self.L.kt_maxpool2x2(self.h, _ptr(x), int(n), int(H), int(W), int(C), _ptr(y),
+                                         _stream(stream)))
 
     def fill_uniform(self, dst, n, seed, offset=0, stream=None):
         self._check(self.L.kt_fill_uniform(self.h, _ptr(dst), int(n), int(seed) & (2 ** 64 - 1),

@@ -112,3 +112,25 @@ def test_splitk_workspace_query_and_host_handle(kt):
     st = h.L.kt_gemm_splitk(h.h, 0, ctypes.byref(s), 4, 1.0, None, 512, 0, None, 8, 0, 0.0, None, 8,
                             0, None, None, 0, None, 0, None, None)
     assert st == -1 and "device" in h.L.kt_last_error(h.h).decode()
+
+
+def test_conv_queries(kt):
+    """The GEMM a convolution runs and its workspace (host-only queries)."""
+    cs = kt.conv_shape(2, 224, 224, 3, 64)
+    assert kt.Handle.conv_gemm_shape(cs, kt.CONV_IM2COL) == (2 * 224 * 224, 64, 27, 1, 0, 0)
+    assert kt.Handle.conv_gemm_shape(cs, kt.CONV_WINOGRAD) == (2 * 112 * 112, 64, 3, 16, 0, 0)
+    assert kt.Handle.conv_workspace_bytes(cs, kt.CONV_IM2COL) == 2 * 224 * 224 * 27 * 4
+    T = 2 * 112 * 112
+    a = lambda v: -(-v // 256) * 256
+    assert kt.Handle.conv_workspace_bytes(cs, kt.CONV_WINOGRAD) == (a(16 * T * 3 * 4) + a(16 * 3 * 64 * 4)
+                                                                   + a(16 * T * 64 * 4))
+    # strided / larger filters: im2col only
+    cs = kt.conv_shape(1, 15, 15, 8, 8, 5, 5, 2, 2)
+    assert kt.Handle.conv_gemm_shape(cs, kt.CONV_IM2COL) == (64, 8, 200, 1, 0, 0)
+    with pytest.raises(kt.KtError):
+        kt.Handle.conv_gemm_shape(cs, kt.CONV_WINOGRAD)
+    with pytest.raises(kt.KtError):
+        kt.Handle.conv_workspace_bytes(kt.conv_shape(1, 8, 8, 0, 4), kt.CONV_IM2COL)
+    h = kt.Handle(-1)
+    with pytest.raises(kt.KtError):
+        h.conv2d(kt.CONV_IM2COL, kt.conv_shape(1, 8, 8, 4, 4), 8, 8, None, False, 8, 8, 1 << 20)
