@@ -243,11 +243,12 @@ VGG16_FC = [(7 * 7 * 512, 4096), (4096, 4096), (4096, 1000)]
 def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
     """Single-image VGG16 inference (224x224x3, random weights scaled by
     1/sqrt(fan-in), FP32, NHWC): 13 3x3 convolutions with ReLU, 5 max pools,
-    3 fully connected layers run as 1x1 convolutions of a 1x1 image.  Every
-    GEMM's configuration comes from the deployed selector (config -1); the
-    3x3 convolutions are timed with im2col and with Winograd F(2x2,3x3), and
-    each layer's GEMM is also run with every configuration to give the
-    exhaustive-best time of the same lowering."""
+    3 fully connected layers run as 1x1 convolutions of a 1x1 image.  Per
+    layer: the deployed selector's configuration (config -1) with im2col,
+    with im2col and automatic split-K, and with Winograd F(2x2,3x3) for the
+    3x3 layers; and every configuration of each lowering (plus split counts
+    2..32 for the M = 1 fully connected layers) for the exhaustive best.  The
+    inference is then timed end to end with each per-layer choice."""
     layers = []   # (kind, conv_shape)
     H, C = 224, 3
     for v in VGG16_CONV:
@@ -260,8 +261,10 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
     for (fi, fo) in VGG16_FC:
         layers.append(("fc", kt.conv_shape(1, 1, 1, fi, fo, 1, 1, 1, 0)))
     convs = [cs for kind, cs in layers if kind != "pool"]
-    ws_bytes = max(kt.Handle.conv_workspace_bytes(cs, al) for cs in convs
-                   for al in ((kt.CONV_IM2COL, kt.CONV_WINOGRAD) if cs.R == 3 else (kt.CONV_IM2COL,)))
+    ws_bytes = max(max(kt.Handle.conv_workspace_bytes(cs, kt.CONV_IM2COL, sp) for sp in (0, 1, 32))
+                   for cs in convs)
+    ws_bytes = max([ws_bytes] + [kt.Handle.conv_workspace_bytes(cs, kt.CONV_WINOGRAD)
+                                 for cs in convs if cs.R == 3])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     weights, biases = [], []
     for i, cs in enumerate(convs):
@@ -277,8 +280,10 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
     h.fill_uniform(x0, x0.numel(), synth.operand_seed(synth.SEED + 99, 0), stream=stream)
     buf = [torch.empty(224 * 224 * 64, dtype=torch.float32, device="cuda") for _ in range(2)]
     flops = sum(2.0 * cs.H * cs.W * cs.Cout * cs.R * cs.S * cs.Cin for cs in convs)
+    last = len(convs) - 1
 
-    def forward(algo_of, cfg_of=lambda li: -1):
+    def forward(choice):
+        """choice[li] = (algo, config_id, splits)."""
         src, li = x0, 0
         for kind, cs in layers:
             dst = buf[0] if src is not buf[0] else buf[1]
@@ -286,8 +291,9 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
                 Hp, Cp = cs
                 h.maxpool2x2(src, 1, Hp, Hp, Cp, dst, stream=stream)
             else:
-                h.conv2d(algo_of(li, cs), cs, src, weights[li], biases[li], kind == "conv" or li < len(convs) - 1,
-                         dst, ws, ws_bytes, config_id=cfg_of(li), stream=stream)
+                algo, cid, sp = choice[li]
+                h.conv2d(algo, cs, src, weights[li], biases[li], li < last, dst, ws, ws_bytes,
+                         config_id=cid, splits=sp, stream=stream)
                 li += 1
             src = dst
         return src
@@ -304,53 +310,53 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
         e1.synchronize()
         return e0.elapsed_time(e1) / n
 
-    def wino_if_3x3(li, cs):
-        return kt.CONV_WINOGRAD if cs.R == 3 else kt.CONV_IM2COL
-
-    # per-layer times: selector pick and exhaustive best, for each lowering
-    per = []
-    src = x0
     cfgs = h.configs()
-    li = 0
-    for kind, cs in layers:
-        if kind == "pool":
-            continue
+    per, sel_choice, ex_choice = [], [], []
+    for li, cs in enumerate(convs):
         xin = torch.empty(cs.H * cs.W * cs.Cin, dtype=torch.float32, device="cuda")
         h.fill_uniform(xin, xin.numel(), synth.operand_seed(synth.SEED + 200 + li, 0), stream=stream)
         out = torch.empty(cs.H * cs.W * cs.Cout, dtype=torch.float32, device="cuda")
-        row = {"layer": li, "H": cs.H, "Cin": cs.Cin, "Cout": cs.Cout}
-        for algo, name in ((kt.CONV_IM2COL, "im2col"), (kt.CONV_WINOGRAD, "winograd")):
-            if algo == kt.CONV_WINOGRAD and cs.R != 3:
-                continue
-            sel = timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out, ws,
-                                         ws_bytes, stream=stream), reps)
-            best = min((timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out, ws,
-                                               ws_bytes, config_id=c, stream=stream), cfg_reps), c)
-                       for c in range(len(cfgs)))
-            row[name] = {"ms_selected": round(sel, 4), "ms_exhaustive": round(best[0], 4),
-                         "exhaustive_config": list(cfgs[best[1]]),
-                         "gemm": list(kt.Handle.conv_gemm_shape(cs, algo)[:4])}
+
+        def run(algo, cid, sp):
+            return timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out, ws,
+                                          ws_bytes, config_id=cid, splits=sp, stream=stream), cfg_reps)
+        row = {"layer": li, "H": cs.H, "Cin": cs.Cin, "Cout": cs.Cout, "R": cs.R}
+        sel_opts, ex_opts = [], []
+        lowerings = [(kt.CONV_IM2COL, "im2col")] + ([(kt.CONV_WINOGRAD, "winograd")] if cs.R == 3 else [])
+        for algo, name in lowerings:
+            t_sel = timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out, ws,
+                                           ws_bytes, stream=stream), reps)
+            sel_opts.append((t_sel, (algo, -1, 1)))
+            ent = {"ms_selected": round(t_sel, 4)}
+            if algo == kt.CONV_IM2COL:
+                t_auto = timed(lambda: h.conv2d(algo, cs, xin, weights[li], biases[li], True, out,
+                                                ws, ws_bytes, splits=0, stream=stream), reps)
+                sel_opts.append((t_auto, (algo, -1, 0)))
+                ent["ms_selected_auto_split"] = round(t_auto, 4)
+            split_set = (1, 2, 4, 8, 16, 32) if (algo == kt.CONV_IM2COL and cs.H == 1) else (1,)
+            best = min((run(algo, c, sp), (algo, c, sp)) for sp in split_set for c in range(len(cfgs)))
+            ex_opts.append(best)
+            ent.update({"ms_exhaustive": round(best[0], 4), "exhaustive_config": list(cfgs[best[1][1]]),
+                        "exhaustive_splits": best[1][2],
+                        "gemm": list(kt.Handle.conv_gemm_shape(cs, algo)[:4])})
+            row[name] = ent
+        sel_choice.append(min(sel_opts)[1])
+        ex_choice.append(min(ex_opts)[1])
         per.append(row)
-        li += 1
-    best_algo = {r["layer"]: (kt.CONV_WINOGRAD if "winograd" in r and
-                              r["winograd"]["ms_selected"] < r["im2col"]["ms_selected"]
-                              else kt.CONV_IM2COL) for r in per}
-    ex_cfg = {}
-    for r in per:
-        nm = "winograd" if best_algo[r["layer"]] == kt.CONV_WINOGRAD else "im2col"
-        ex_cfg[r["layer"]] = cfgs.index(tuple(r[nm]["exhaustive_config"]))
     ms = {
-        "im2col_selected": timed(lambda: forward(lambda li, cs: kt.CONV_IM2COL), reps),
-        "winograd_selected": timed(lambda: forward(wino_if_3x3), reps),
-        "best_lowering_selected": timed(lambda: forward(lambda li, cs: best_algo[li]), reps),
-        "best_lowering_exhaustive": timed(lambda: forward(lambda li, cs: best_algo[li],
-                                                          lambda li: ex_cfg[li]), reps),
+        "im2col_selected": timed(lambda: forward([(kt.CONV_IM2COL, -1, 1)] * len(convs)), reps),
+        "winograd_selected": timed(lambda: forward([(kt.CONV_WINOGRAD if cs.R == 3 else kt.CONV_IM2COL,
+                                                     -1, 1) for cs in convs]), reps),
+        "best_lowering_selected": timed(lambda: forward(sel_choice), reps),
+        "best_lowering_exhaustive": timed(lambda: forward(ex_choice), reps),
     }
     torch.cuda.synchronize()
+    names = {kt.CONV_IM2COL: "im2col", kt.CONV_WINOGRAD: "winograd"}
     return {"ms_per_inference": {kk: round(v, 4) for kk, v in ms.items()},
             "gflop_direct": round(flops / 1e9, 2),
             "tflops_effective_best_lowering_selected": round(flops / (ms["best_lowering_selected"] * 1e-3) / 1e12, 2),
             "selected_pct_of_exhaustive": round(100 * ms["best_lowering_exhaustive"] / ms["best_lowering_selected"], 2),
+            "selected_choice": [[names[a], sp] for a, _, sp in sel_choice],
             "layers": per}
 
 

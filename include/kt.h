@@ -146,9 +146,13 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
  * shape M, N, kc with batch * S items) into FP32 partial planes in the
  * workspace (device, dense, [S][batch][M][N]), and one reduction pass writes
  * C = alpha * (sum of the planes in slice order) + beta * C (C not read when
- * beta == 0).  Arguments and layouts as kt_gemm; 1 <= splits <= 64.  When
- * S == 1 (splits == 1 or K <= 64) this is exactly kt_gemm and needs no
- * workspace.  *used_splits (host, may be NULL) receives S.  The workspace
+ * beta == 0).  Arguments and layouts as kt_gemm; 0 <= splits <= 64.
+ * splits == 0 chooses S: the configuration is config_id, or the selector's
+ * pick for the whole product, and S doubles from 1 while that configuration
+ * fills fewer than 512 work-groups (tiles x batch x S), each slice stays at
+ * least 256 deep and S < 64.  When S == 1 (also splits == 1 or K <= 64)
+ * this is exactly kt_gemm and needs no workspace.  *used_splits (host, may
+ * be NULL) receives S.  The workspace
  * must stay untouched until the work on `stream` has finished.
  * KT_EWORKSPACE if it is smaller than kt_gemm_splitk_workspace_bytes. */
 kt_status kt_gemm_splitk(kt_handle h, kt_dtype in_dtype, const kt_shape* s, int32_t splits,
@@ -158,7 +162,8 @@ kt_status kt_gemm_splitk(kt_handle h, kt_dtype in_dtype, const kt_shape* s, int3
                          int32_t config_id, void* workspace, size_t ws_bytes, void* stream,
                          int32_t* used_splits);
 /* Workspace bytes of kt_gemm_splitk: splits * batch * M * N floats, rounded
- * up to 256 bytes (0 for splits == 1).  Host only. */
+ * up to 256 bytes (0 for splits == 1); for splits == 0 a bound that covers
+ * every automatic choice, min(64 * batch * M * N, 2^26) floats.  Host only. */
 kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size_t* bytes);
 
 /* ------------------------------------------------------------ convolution */
@@ -186,17 +191,24 @@ typedef struct {
  * im2col {n Ho Wo, Cout, R S Cin, batch 1}, Winograd {T, Cout, Cin, batch 16},
  * both non-transposed.  Host only. */
 kt_status kt_conv2d_gemm_shape(const kt_conv_shape* c, kt_conv_algo algo, kt_shape* out);
-/* Device workspace of kt_conv2d (im2col: the patch matrix; Winograd: the
+/* Device workspace of kt_conv2d for a `splits` value (im2col: the patch
+ * matrix, none for a 1x1 filter with stride 1 and no padding, whose patch
+ * matrix is x itself, followed by the split-K partial planes of
+ * kt_gemm_splitk_workspace_bytes when splits != 1; Winograd: the
  * transformed input, filter and the 16 products, each 256-byte aligned). */
-kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, size_t* bytes);
+kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, int32_t splits,
+                                    size_t* bytes);
 /* y = conv(x, w) + bias, then ReLU when relu != 0.  x, w, bias (NULL = no
  * bias; Cout floats), y and workspace are device pointers; y must not alias
  * x or the workspace.  config_id: FP32 configuration of the GEMM, -1 = the
- * fitted selector on kt_conv2d_gemm_shape.  Empty n, Ho or Wo is a no-op.
- * Asynchronous on `stream`. */
+ * fitted selector on kt_conv2d_gemm_shape.  splits (im2col only; Winograd
+ * takes 0 or 1 and never splits): 1 = the plain GEMM, otherwise the GEMM
+ * runs as kt_gemm_splitk with this splits value (0 = automatic), which suits
+ * the fully connected layers of a single image (M = 1, deep K).  Empty n, Ho
+ * or Wo is a no-op.  Asynchronous on `stream`. */
 kt_status kt_conv2d(kt_handle h, kt_conv_algo algo, const kt_conv_shape* c, const float* x,
                     const float* w, const float* bias, int32_t relu, float* y, int32_t config_id,
-                    void* workspace, size_t ws_bytes, void* stream);
+                    int32_t splits, void* workspace, size_t ws_bytes, void* stream);
 /* 2x2 max pooling with stride 2 on NHWC FP32 (device): y is
  * (n, H/2, W/2, C); an odd trailing row or column is dropped. */
 kt_status kt_maxpool2x2(kt_handle h, const float* x, int64_t n, int64_t H, int64_t W, int64_t C,

@@ -89,9 +89,10 @@ _SIGS = {
                                c_i32, c_vp, c_sz, c_vp, ctypes.POINTER(c_i32)]),
     "kt_gemm_splitk_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
     "kt_conv2d_gemm_shape": (c_i32, [ctypes.POINTER(ConvShape), c_i32, ctypes.POINTER(Shape)]),
-    "kt_conv2d_workspace_bytes": (c_i32, [ctypes.POINTER(ConvShape), c_i32, ctypes.POINTER(c_sz)]),
+    "kt_conv2d_workspace_bytes": (c_i32, [ctypes.POINTER(ConvShape), c_i32, c_i32,
+                                          ctypes.POINTER(c_sz)]),
     "kt_conv2d": (c_i32, [c_vp, c_i32, ctypes.POINTER(ConvShape), c_vp, c_vp, c_vp, c_i32, c_vp,
-                          c_i32, c_vp, c_sz, c_vp]),
+                          c_i32, c_i32, c_vp, c_sz, c_vp]),
     "kt_maxpool2x2": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
     "kt_convert_bf16": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
@@ -321,18 +322,20 @@ class Handle:
         return (out.M, out.N, out.K, out.batch, out.transA, out.transB)
 
     @staticmethod
-    def conv_workspace_bytes(c: ConvShape, algo) -> int:
+    def conv_workspace_bytes(c: ConvShape, algo, splits=1) -> int:
         b = c_sz()
-        st = lib().kt_conv2d_workspace_bytes(ctypes.byref(c), int(algo), ctypes.byref(b))
+        st = lib().kt_conv2d_workspace_bytes(ctypes.byref(c), int(algo), int(splits),
+                                             ctypes.byref(b))
         if st != 0:
             raise KtError(st, "conv workspace query")
         return b.value
 
     def conv2d(self, algo, c: ConvShape, x, w, bias, relu, y, workspace, ws_bytes, config_id=-1,
-               stream=None):
+               splits=1, stream=None):
         self._check(self.L.kt_conv2d(self.h, int(algo), ctypes.byref(c), _ptr(x), _ptr(w),
                                      _ptr(bias), int(bool(relu)), _ptr(y), int(config_id),
-                                     _ptr(workspace), int(ws_bytes), _stream(stream)))
+                                     int(splits), _ptr(workspace), int(ws_bytes),
+                                     _stream(stream)))
 
     def maxpool2x2(self, x, n, H, W, C, y, stream=None):
         self._check(self.L.kt_maxpool2x2(self.h, _ptr(x), int(n), int(H), int(W), int(C), _ptr(y),

@@ -228,12 +228,36 @@ void conv_gemm_shape(const ConvDims& d, kt_conv_algo algo, kt_shape* s) {
   }
 }
 
-size_t conv_ws_bytes(const ConvDims& d, kt_conv_algo algo) {
+// A 1x1 filter with stride 1 and no padding: the patch matrix is x itself.
+bool pointwise(const ConvDims& d) { return d.R == 1 && d.S == 1 && d.st == 1 && d.pad == 0; }
+
+// Patch matrix (im2col, none for pointwise layers) or transforms (Winograd).
+size_t conv_main_bytes(const ConvDims& d, kt_conv_algo algo) {
   kt_shape s;
   conv_gemm_shape(d, algo, &s);
-  if (algo == KT_CONV_IM2COL) return a256((size_t)s.M * s.K * 4);
+  if (algo == KT_CONV_IM2COL) return pointwise(d) ? 0 : a256((size_t)s.M * s.K * 4);
   return a256((size_t)16 * s.M * d.C * 4) + a256((size_t)16 * d.C * d.O * 4) +
          a256((size_t)16 * s.M * d.O * 4);
+}
+
+kt_status check_splits(Ctx* h, kt_conv_algo algo, int32_t splits) {
+  if (splits < 0 || splits > 64) return fail(h, KT_EINVAL, "need 0 <= splits <= 64");
+  if (algo == KT_CONV_WINOGRAD && splits > 1)
+    return fail(h, KT_EUNSUPPORTED, "split-K is offered for the im2col lowering only");
+  return KT_OK;
+}
+
+// Total workspace: the main part, then the split-K partial planes.
+kt_status conv_ws_bytes(Ctx* h, const ConvDims& d, kt_conv_algo algo, int32_t splits, size_t* out) {
+  size_t extra = 0;
+  if (algo == KT_CONV_IM2COL && splits != 1) {
+    kt_shape s;
+    conv_gemm_shape(d, algo, &s);
+    kt_status st = kt_gemm_splitk_workspace_bytes(&s, splits, &extra);
+    if (st != KT_OK) return fail(h, st, "split-K workspace query");
+  }
+  *out = conv_main_bytes(d, algo) + extra;
+  return KT_OK;
 }
 
 }  // namespace
@@ -253,44 +277,58 @@ kt_status kt_conv2d_gemm_shape(const kt_conv_shape* c, kt_conv_algo algo, kt_sha
   return KT_OK;
 }
 
-kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, size_t* bytes) {
+kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, int32_t splits,
+                                    size_t* bytes) {
   ConvDims d;
   if (!bytes) return fail(nullptr, KT_EINVAL, "bytes is NULL");
   kt_status st = check_conv(nullptr, algo, c, &d);
+  if (st == KT_OK) st = check_splits(nullptr, algo, splits);
   if (st != KT_OK) return st;
-  *bytes = conv_ws_bytes(d, algo);
-  return KT_OK;
+  return conv_ws_bytes(nullptr, d, algo, splits, bytes);
 }
 
 kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, const float* x,
                     const float* w, const float* bias, int32_t relu, float* y, int32_t config_id,
-                    void* workspace, size_t ws_bytes, void* stream) {
+                    int32_t splits, void* workspace, size_t ws_bytes, void* stream) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!need_device(h)) return KT_EINVAL;
   ConvDims d;
   kt_status st = check_conv(h, algo, c, &d);
+  if (st == KT_OK) st = check_splits(h, algo, splits);
   if (st != KT_OK) return st;
   if (d.n == 0 || d.Ho == 0 || d.Wo == 0) return KT_OK;
   if (!x || !w || !y) return fail(h, KT_EINVAL, "x, w or y is NULL");
-  const size_t need = conv_ws_bytes(d, algo);
-  if (!workspace || ws_bytes < need) return fail(h, KT_EWORKSPACE, "conv workspace too small");
+  size_t need = 0;
+  if ((st = conv_ws_bytes(h, d, algo, splits, &need)) != KT_OK) return st;
+  if (need > 0 && (!workspace || ws_bytes < need))
+    return fail(h, KT_EWORKSPACE, "conv workspace too small");
   if (config_id >= (int32_t)h->configs[KT_F32].size())
     return fail(h, KT_EINVAL, "config id out of range");
   kt_shape gs;
   conv_gemm_shape(d, algo, &gs);
-  int32_t cfg = config_id;
-  if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
   hipError_t e;
   if (algo == KT_CONV_IM2COL) {
-    float* col = (float*)ws;
-    hipLaunchKernelGGL(im2col_kernel, dim3(grid_for(gs.M)), dim3(CT), 0, s, x, d, col);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "im2col launch");
+    const float* col = x;
+    if (!pointwise(d)) {
+      hipLaunchKernelGGL(im2col_kernel, dim3(grid_for(gs.M)), dim3(CT), 0, s, x, d, (float*)ws);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "im2col launch");
+      col = (const float*)ws;
+    }
     // y (P x O) = col (P x RSC) * w (RSC x O)
-    st = launch_gemm(h, KT_F32, &gs, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O, 0.f, y, d.O,
-                     gs.M * d.O, nullptr, nullptr, cfg, s);
+    if (splits == 1) {
+      int32_t cfg = config_id;
+      if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
+      st = launch_gemm(h, KT_F32, &gs, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O, 0.f, y,
+                       d.O, gs.M * d.O, nullptr, nullptr, cfg, s);
+    } else {
+      const size_t main = conv_main_bytes(d, algo);
+      st = kt_gemm_splitk(hh, KT_F32, &gs, splits, 1.f, col, gs.K, gs.M * gs.K, w, d.O,
+                          gs.K * d.O, 0.f, y, d.O, gs.M * d.O, nullptr, nullptr, config_id,
+                          ws + main, ws_bytes - main, stream, nullptr);
+    }
     if (st != KT_OK) return st;
     if (bias || relu) {
       hipLaunchKernelGGL(bias_act_kernel, dim3(grid_for(cdiv(gs.M * d.O, CT))), dim3(CT), 0, s, y,
@@ -299,6 +337,8 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
     }
     return KT_OK;
   }
+  int32_t cfg = config_id;
+  if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
   const int64_t tH = (d.Ho + 1) / 2, tW = (d.Wo + 1) / 2, T = gs.M;
   float* V = (float*)ws;
   float* U = (float*)(ws + a256((size_t)16 * T * d.C * 4));

@@ -34,6 +34,18 @@ size_t plane_bytes(const kt_shape* s) { return (size_t)s->batch * s->M * s->N * 
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Automatic slice count: double S while the launch has fewer than 512
+// work-groups (two per compute unit), the slices stay at least 256 deep and
+// S < 64.  Hence S * tiles < 1024, which bounds the workspace (below).
+int32_t auto_splits(int64_t tiles, int64_t K) {
+  int32_t S = 1;
+  while (tiles * S < 512 && S < SPLITK_MAX && K / (2 * S) >= 256) S *= 2;
+  return S;
+}
+
+// Largest tile area of any configuration (256 x 256 low-precision tiles).
+constexpr int64_t MAX_TILE_AREA = 256 * 256;
+
 // C[b][i][j] = alpha * sum_s W[s][b][i][j] + beta * C[b][i][j]; C is not
 // read when beta is 0.  Each work-group covers RED_THREADS consecutive
 // columns of one output row, so plane reads and C accesses are coalesced.
@@ -68,9 +80,15 @@ extern "C" {
 
 kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size_t* bytes) {
   if (!s || !bytes) return fail(nullptr, KT_EINVAL, "NULL argument");
-  if (splits < 1 || splits > SPLITK_MAX) return fail(nullptr, KT_EINVAL, "need 1 <= splits <= 64");
+  if (splits < 0 || splits > SPLITK_MAX) return fail(nullptr, KT_EINVAL, "need 0 <= splits <= 64");
   if (s->M < 0 || s->N < 0 || s->K < 0 || s->batch < 0)
     return fail(nullptr, KT_EINVAL, "negative M, N, K or batch");
+  if (splits == 0) {   // automatic: S * plane <= S * tiles * tile area < 1024 * MAX_TILE_AREA
+    const size_t cap = (size_t)1024 * MAX_TILE_AREA * 4;
+    const size_t all = (size_t)SPLITK_MAX * plane_bytes(s);
+    *bytes = a256(all < cap ? all : cap);
+    return KT_OK;
+  }
   *bytes = splits == 1 ? 0 : a256((size_t)splits * plane_bytes(s));
   return KT_OK;
 }
@@ -85,7 +103,7 @@ kt_status kt_gemm_splitk(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!need_device(h)) return KT_EINVAL;
   if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
-  if (splits < 1 || splits > SPLITK_MAX) return fail(h, KT_EINVAL, "need 1 <= splits <= 64");
+  if (splits < 0 || splits > SPLITK_MAX) return fail(h, KT_EINVAL, "need 0 <= splits <= 64");
   kt_status st = check_gemm_args(h, s, lda, strideA, ldb, strideB, ldc, strideC);
   if (st != KT_OK) return st;
   if (used_splits) *used_splits = 1;
@@ -99,6 +117,11 @@ kt_status kt_gemm_splitk(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_
   hipStream_t stream_h = (hipStream_t)stream;
 
   const int64_t K = s->K;
+  if (splits == 0) {   // automatic: the configuration first (selector on the whole product)
+    if (config_id < 0 && (st = select_config(h, dtype, s, &config_id)) != KT_OK) return st;
+    const ConfigDef& c = h->configs[dtype][config_id];
+    splits = auto_splits(cdiv(s->M, c.bm) * cdiv(s->N, c.bn) * s->batch, K);
+  }
   const int64_t kc = K > 0 ? slice_depth(K, splits) : 0;
   const int32_t S = K > 0 ? (int32_t)cdiv(K, kc) : 1;
   if (S <= 1) {   // one slice: the plain product, no workspace

@@ -33,16 +33,16 @@ def _data(n, H, W, C, O, R, S, seed):
     return x, w, b
 
 
-def _run(h, torch, algo, cs, x, w, b, relu, cfg):
+def _run(h, torch, algo, cs, x, w, b, relu, cfg, splits=1):
     import paper_2008_13145_amd as kt
     Ho, Wo = oc.out_size(cs.H, cs.R, cs.stride, cs.pad), oc.out_size(cs.W, cs.S, cs.stride, cs.pad)
-    ws_bytes = kt.Handle.conv_workspace_bytes(cs, algo)
+    ws_bytes = kt.Handle.conv_workspace_bytes(cs, algo, splits)
     ws = torch.empty(max(ws_bytes, 4), dtype=torch.uint8, device="cuda")
     dx = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
     dw = torch.from_numpy(np.ascontiguousarray(w, np.float32)).cuda()
     db = None if b is None else torch.from_numpy(np.ascontiguousarray(b, np.float32)).cuda()
     dy = torch.full((cs.n, max(Ho, 0), max(Wo, 0), cs.Cout), float("nan"), device="cuda")
-    h.conv2d(algo, cs, dx, dw, db, relu, dy, ws, ws_bytes, config_id=cfg)
+    h.conv2d(algo, cs, dx, dw, db, relu, dy, ws, ws_bytes, config_id=cfg, splits=splits)
     torch.cuda.synchronize()
     return dy.cpu().numpy()
 
@@ -184,3 +184,24 @@ def test_conv_edge_cases(gpu):
         assert e.value.status == -5
     torch.cuda.synchronize()
     assert bool((y == 5.0).all())
+
+
+@pytest.mark.parametrize("case,splits", [
+    ((1, 1, 1, 2048, 300, 1, 1, 1, 0), 0),     # a fully connected layer: M = 1, automatic split
+    ((1, 1, 1, 4096, 1000, 1, 1, 1, 0), 8),
+    ((3, 6, 7, 64, 33, 1, 1, 1, 0), 1),        # pointwise, no patch matrix
+    ((1, 10, 10, 64, 32, 3, 3, 1, 1), 3),      # 3x3 through split-K
+])
+def test_im2col_split_k_and_pointwise(gpu, case, splits):
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    cs = kt.conv_shape(*case)
+    x, w, b = _data(*case[:7], seed=800 + sum(case))
+    cfg = h.configs().index((64, 64, 4, 16))
+    for relu, bias in ((True, b), (False, None)):
+        ref = oc.conv2d(x, w, bias, cs.stride, cs.pad, relu)
+        got = _run(h, torch, IM2COL, cs, x, w, bias, relu, cfg, splits)
+        assert np.all(np.abs(got - ref) <= _tol(IM2COL, x, w, bias, ref, cs)), (relu, splits)
+    with pytest.raises(kt.KtError) as e:
+        kt.Handle.conv_workspace_bytes(kt.conv_shape(1, 8, 8, 4, 4), WINO, 2)
+    assert e.value.status == -2

@@ -104,9 +104,12 @@ def test_splitk_workspace_query_and_host_handle(kt):
     # splits * batch * M * N floats, 256-aligned; one slice needs none
     assert kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, 8) == -(-8 * 3 * 100 * 70 * 4 // 256) * 256
     assert kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, 1) == 0
-    for bad in (0, 65, -2):
+    for bad in (65, -2):
         with pytest.raises(kt.KtError):
             kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, bad)
+    # automatic (0): bounded by 64 planes and by 1024 tiles of the largest area
+    assert kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, 0) == -(-64 * 3 * 100 * 70 * 4 // 256) * 256
+    assert kt.Handle.splitk_workspace_bytes(4096, 4096, 5000, 1, 0) == 1024 * 256 * 256 * 4
     h = kt.Handle(-1)
     s = kt.shape(8, 8, 512)
     st = h.L.kt_gemm_splitk(h.h, 0, ctypes.byref(s), 4, 1.0, None, 512, 0, None, 8, 0, 0.0, None, 8,
@@ -124,6 +127,13 @@ def test_conv_queries(kt):
     a = lambda v: -(-v // 256) * 256
     assert kt.Handle.conv_workspace_bytes(cs, kt.CONV_WINOGRAD) == (a(16 * T * 3 * 4) + a(16 * 3 * 64 * 4)
                                                                    + a(16 * T * 64 * 4))
+    # a 1x1 filter with stride 1 and no padding multiplies x itself: no patch matrix
+    fc = kt.conv_shape(1, 1, 1, 25088, 4096, 1, 1, 1, 0)
+    assert kt.Handle.conv_gemm_shape(fc, kt.CONV_IM2COL) == (1, 4096, 25088, 1, 0, 0)
+    assert kt.Handle.conv_workspace_bytes(fc, kt.CONV_IM2COL) == 0
+    assert kt.Handle.conv_workspace_bytes(fc, kt.CONV_IM2COL, 8) == -(-8 * 4096 * 4 // 256) * 256
+    with pytest.raises(kt.KtError):
+        kt.Handle.conv_workspace_bytes(kt.conv_shape(1, 8, 8, 4, 4), kt.CONV_WINOGRAD, 2)
     # strided / larger filters: im2col only
     cs = kt.conv_shape(1, 15, 15, 8, 8, 5, 5, 2, 2)
     assert kt.Handle.conv_gemm_shape(cs, kt.CONV_IM2COL) == (64, 8, 200, 1, 0, 0)

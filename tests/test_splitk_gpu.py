@@ -190,3 +190,27 @@ def test_splitk_low_precision(gpu, dtype, ta, tb):
         assert np.all(np.abs(got - ref_q) <= tol)
     else:
         assert cv.rel_frobenius(got[0], ref_q[0]) <= 1e-3
+
+
+def _auto_splits(tiles, K):
+    S = 1
+    while tiles * S < 512 and S < 64 and K // (2 * S) >= 256:
+        S *= 2
+    return S
+
+
+@pytest.mark.parametrize("M,N,K,bt", [(1, 4096, 25088, 1), (1, 1000, 4096, 1), (300, 200, 900, 2),
+                                      (2000, 2000, 3000, 1)])
+def test_splitk_automatic(gpu, M, N, K, bt):
+    """splits = 0: S doubles while the configuration fills fewer than 512
+    work-groups and slices stay >= 256 deep (S < 64); results as in FP32
+    parity."""
+    h, torch = gpu
+    cfg = h.configs().index((64, 64, 4, 16))
+    a, b, c0 = _operands(M, N, K, bt, 40 + M)
+    S = _auto_splits(-(-M // 64) * -(-N // 64) * bt, K)
+    ref = _oracle(a, b, c0, 1.0, 0.0)
+    got, used = _splitk(h, torch, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(),
+                        np.full_like(c0, np.nan), 0, 0, 0, 1.0, 0.0, cfg)
+    assert used == _expected_slices(K, S)
+    assert np.all(np.abs(got - ref) <= _bound(a, b, c0, 1.0, 0.0))
