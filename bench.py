@@ -704,9 +704,22 @@ def main(argv=None):
         pca[str(dims)] = {"explained_variance": round(r_p["explained"], 4),
                           "kmeans_ceiling": round(100 * _geomean(
                               t_best[te_rows] / T[te_rows][:, r_p["chosen"]].min(axis=1)), 2)}
+    # ---- the pruner grid (section 4.3's comparison): every pruning method
+    # under every normalization, ceiling on the held-out rows
+    def ceil_test(ch):
+        return round(100 * _geomean(t_best[te_rows] / T[te_rows][:, ch].min(axis=1)), 2)
+    grid = {"top_n": ceil_test(topn)}
+    for norm, name in enumerate(tune.NORM_NAMES):
+        ch_km = hk.prune(T[tr_rows], k, norm=norm, seed=synth.SEED, n_init=10, max_iter=300,
+                         workspace=pws, ws_bytes=ws_bytes, stream=stream)["chosen"]
+        ch_pca = tune.pca_pruning(hk, T[tr_rows], k, synth.SEED, 16, norm, workspace=pws,
+                                  ws_bytes=ws_bytes, stream=stream)["chosen"]
+        ch_dt = tune.tree_pruning(hk, T[tr_rows], tr_shapes, k, norm, stream=stream)
+        grid[name] = {"kmeans": ceil_test(ch_km), "pca16_kmeans": ceil_test(ch_pca),
+                      "decision_tree": ceil_test(ch_dt)}
     hk.close()
     _log(f"bench: k sweep {json.dumps(k_sweep)}; sparse sampling {json.dumps(sparse)}; "
-         f"pca {json.dumps(pca)}")
+         f"pca {json.dumps(pca)}; pruner grid {json.dumps(grid)}")
     sel_kind = {v: kk for kk, v in SEL_NAMES.items()}[a.selector]
     h.fit_selector(sel_kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
                    workspace=mws, ws_bytes=mws_bytes, stream=stream)
@@ -831,6 +844,7 @@ def main(argv=None):
         "k_sweep_pct_of_optimal_test": k_sweep,
         "sparse_sampling_kmeans_ceiling_test": sparse,
         "pca_kmeans_ceiling_test": pca,
+        "pruner_grid_ceiling_test": grid,
         "gpu_state": {"before": state_before, "after": state_after},
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")

@@ -304,6 +304,26 @@ kt_status kt_kmeans_u16(kt_handle h, const uint16_t* X, int32_t n, int32_t d, in
                         size_t ws_bytes, void* stream, int32_t* labels, int64_t* centroids,
                         int64_t* inertia_out);
 
+/* Decision-tree pruning (section 4.1: a regression tree from the matrix
+ * sizes to the performance vector, limited to k leaves, each leaf's vector
+ * standing for the problems that reach it).  shapes[n] and Xq (n x d
+ * normalized Q16 rows, as written by kt_normalize) are host arrays; the
+ * features are (M, N, K, batch, transA, transB).  A split of a node's rows
+ * into L and R is scored by A / n_L + B / n_R (A, B: squared norms of the
+ * children's column sums; the maximum minimises the squared error to the
+ * children's means), thresholds floor(sqrt(a*b)) between consecutive
+ * distinct values, x <= t goes left, features scanned 0..5 and thresholds
+ * ascending with the first maximum kept.  Growth is best first: while there
+ * are fewer than k leaves, the leaf whose best split gains most over
+ * P / n (lowest node id on ties) is split if that gain is positive.  Leaves
+ * in pre-order pick the configuration with the largest rounded mean
+ * floor((2 s + n) / (2 n)) not already chosen (lowest index on ties); with
+ * fewer than k leaves the rest are the unchosen columns with the largest
+ * sums.  chosen[k] (host) receives the picks.  Host only (works on a handle
+ * without a device); n <= 4096, k <= d <= 256 (KT_EUNSUPPORTED beyond). */
+kt_status kt_prune_tree(kt_handle h, const kt_shape* shapes, const uint16_t* Xq, int32_t n,
+                        int32_t d, int32_t k, int32_t* chosen);
+
 /* Top-N baseline of section 4.2: the k configurations that are best (largest
  * relative value, lowest index on ties) for the most rows, ties in the count
  * to the lower index.  time_ns and chosen are host arrays; the workspace is

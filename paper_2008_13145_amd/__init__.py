@@ -105,6 +105,7 @@ _SIGS = {
     "kt_prune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                          c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
     "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp, c_vp]),
+    "kt_prune_tree": (c_i32, [c_vp, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_i32, c_vp]),
     "kt_kmeans_u16": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                               c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "kt_fit_selector": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp,
@@ -417,6 +418,17 @@ class Handle:
                                          _ptr(workspace), int(ws_bytes), _stream(stream),
                                          chosen.ctypes.data))
         return chosen.tolist()
+
+    def prune_tree(self, shapes, Xq, k):
+        """Decision-tree pruning of the normalized Q16 table Xq (n x d host
+        array, e.g. from normalize()) over the problem shapes; returns the k
+        chosen configuration ids."""
+        Xq = np.ascontiguousarray(np.asarray(Xq).astype(np.uint16))
+        n, d = Xq.shape
+        arr = shapes_array(shapes)
+        out = np.zeros(k, dtype=np.int32)
+        self._check(self.L.kt_prune_tree(self.h, arr, Xq.ctypes.data, n, d, int(k), out.ctypes.data))
+        return [int(v) for v in out]
 
     def kmeans_u16(self, X, k, seed=13145, n_init=10, max_iter=300, workspace=None, ws_bytes=0,
                    stream=None):

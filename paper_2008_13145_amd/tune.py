@@ -84,6 +84,25 @@ def clusters_to_configs(Xq, labels, k):
     return chosen
 
 
+def normalized_table(h, T, norm, stream=None):
+    """The Q16 normalized table (section 3.4) computed on the GPU, as a host
+    uint16 array."""
+    import torch
+    T = np.ascontiguousarray(T, dtype=np.int64)
+    n, d = T.shape
+    dT = torch.from_numpy(T).cuda()
+    out = torch.zeros((n, d), dtype=torch.int16, device="cuda")
+    h.normalize(dT, n, d, norm, out, stream=stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint16)
+
+
+def tree_pruning(h, T_train, shapes, k, norm, stream=None):
+    """Decision-tree pruning (section 4.1): GPU normalization, then the
+    library's regression tree over the problem shapes."""
+    return h.prune_tree(shapes, normalized_table(h, T_train, norm, stream), k)
+
+
 def pca_pruning(h, T_train, k, seed, dims, norm, n_init=10, max_iter=300, workspace=None,
                 ws_bytes=0, stream=None):
     """k-means pruning in a reduced space (section 4.1: principal components
@@ -93,14 +112,7 @@ def pca_pruning(h, T_train, k, seed, dims, norm, n_init=10, max_iter=300, worksp
     (so Euclidean geometry is kept), clustered with the library's integer
     k-means, and each cluster mapped back to a configuration by
     clusters_to_configs.  Returns {"chosen", "inertia", "explained"}."""
-    import torch
-    T_train = np.ascontiguousarray(T_train, dtype=np.int64)
-    n, d = T_train.shape
-    dT = torch.from_numpy(T_train).cuda()
-    out = torch.zeros((n, d), dtype=torch.int16, device="cuda")
-    h.normalize(dT, n, d, norm, out, stream=stream)
-    torch.cuda.synchronize()
-    Xq = out.cpu().numpy().view(np.uint16).astype(np.int64)
+    Xq = normalized_table(h, T_train, norm, stream).astype(np.int64)
     Xf = Xq / 65535.0
     Xc = Xf - Xf.mean(axis=0)
     _, S, Vt = np.linalg.svd(Xc, full_matrices=False)

@@ -360,3 +360,19 @@ def test_pca_pruning_matches_oracle_steps(gpu):
     assert got["inertia"] == ref["inertia"]
     assert got["chosen"] == okm.centroids_to_configs(C)
     assert 0 < got["explained"] <= 1
+
+
+@pytest.mark.parametrize("norm", [0, 2])
+def test_tree_pruning_on_gpu_normalized_table(gpu, norm):
+    """Decision-tree pruning fed by the GPU normalization equals the oracle's
+    normalization followed by the oracle's tree, pick for pick."""
+    from oracle import prune_tree as opt
+    from paper_2008_13145_amd import tune
+    h, torch = gpu
+    T, P, C, meta = tune.load_table(tune.DEFAULT_TABLE)
+    train, _ = synth.train_test_split()
+    rows = synth.rows_of_shapes(train)
+    shapes = [tuple(int(v) for v in P[r]) for r in rows]
+    got = tune.tree_pruning(h, T[rows], shapes, 8, norm)
+    want = opt.prune(P[rows], onz.normalize(T[rows].astype(np.int64), norm), 8)
+    assert got == want
