@@ -282,18 +282,18 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
     flops = sum(2.0 * cs.H * cs.W * cs.Cout * cs.R * cs.S * cs.Cin for cs in convs)
     last = len(convs) - 1
 
-    def forward(choice):
+    def forward(choice, st=stream):
         """choice[li] = (algo, config_id, splits)."""
         src, li = x0, 0
         for kind, cs in layers:
             dst = buf[0] if src is not buf[0] else buf[1]
             if kind == "pool":
                 Hp, Cp = cs
-                h.maxpool2x2(src, 1, Hp, Hp, Cp, dst, stream=stream)
+                h.maxpool2x2(src, 1, Hp, Hp, Cp, dst, stream=st)
             else:
                 algo, cid, sp = choice[li]
                 h.conv2d(algo, cs, src, weights[li], biases[li], li < last, dst, ws, ws_bytes,
-                         config_id=cid, splits=sp, stream=stream)
+                         config_id=cid, splits=sp, stream=st)
                 li += 1
             src = dst
         return src
@@ -350,6 +350,16 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
         "best_lowering_selected": timed(lambda: forward(sel_choice), reps),
         "best_lowering_exhaustive": timed(lambda: forward(ex_choice), reps),
     }
+    # the selected inference captured once in a graph and replayed
+    out_eager = forward(sel_choice).clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out_buf = forward(sel_choice, torch.cuda.current_stream())
+    g.replay()
+    torch.cuda.synchronize()
+    graph_ok = bool(torch.equal(out_buf, out_eager))
+    ms["best_lowering_selected_graph"] = timed(g.replay, reps)
     torch.cuda.synchronize()
     names = {kt.CONV_IM2COL: "im2col", kt.CONV_WINOGRAD: "winograd"}
     return {"ms_per_inference": {kk: round(v, 4) for kk, v in ms.items()},
@@ -357,6 +367,7 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
             "tflops_effective_best_lowering_selected": round(flops / (ms["best_lowering_selected"] * 1e-3) / 1e12, 2),
             "selected_pct_of_exhaustive": round(100 * ms["best_lowering_exhaustive"] / ms["best_lowering_selected"], 2),
             "selected_choice": [[names[a], sp] for a, _, sp in sel_choice],
+            "graph_replay_matches_eager": graph_ok,
             "layers": per}
 
 

@@ -205,3 +205,50 @@ def test_im2col_split_k_and_pointwise(gpu, case, splits):
     with pytest.raises(kt.KtError) as e:
         kt.Handle.conv_workspace_bytes(kt.conv_shape(1, 8, 8, 4, 4), WINO, 2)
     assert e.value.status == -2
+
+
+def test_graph_captured_stack_matches_eager(gpu):
+    """A small stack (Winograd 3x3 conv + ReLU, 2x2 pool, fully connected
+    layer through automatic split-K) captured in one graph: three replays,
+    with eager work on other data between them, each equal bit for bit to
+    the eager result and within the oracle bound."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    cfg = h.configs().index((64, 64, 4, 16))
+    c1 = kt.conv_shape(1, 16, 16, 8, 32)
+    fc = kt.conv_shape(1, 1, 1, 8 * 8 * 32, 100, 1, 1, 1, 0)
+    x, w1, b1 = _data(1, 16, 16, 8, 32, 3, 3, seed=91)
+    _, w2, b2 = _data(1, 1, 1, 8 * 8 * 32, 100, 1, 1, seed=92)
+    ws_bytes = max(kt.Handle.conv_workspace_bytes(c1, WINO), kt.Handle.conv_workspace_bytes(fc, IM2COL, 0))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    dx = torch.from_numpy(x).cuda()
+    dw1, db1 = torch.from_numpy(w1).cuda(), torch.from_numpy(b1).cuda()
+    dw2, db2 = torch.from_numpy(w2).cuda(), torch.from_numpy(b2).cuda()
+    a1 = torch.empty((1, 16, 16, 32), device="cuda")
+    p1 = torch.empty((1, 8, 8, 32), device="cuda")
+    y = torch.empty((1, 1, 1, 100), device="cuda")
+
+    def net(inp, st):
+        h.conv2d(WINO, c1, inp, dw1, db1, True, a1, ws, ws_bytes, config_id=cfg, stream=st)
+        h.maxpool2x2(a1, 1, 16, 16, 32, p1, stream=st)
+        h.conv2d(IM2COL, fc, p1, dw2, db2, False, y, ws, ws_bytes, config_id=cfg, splits=0, stream=st)
+
+    net(dx, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    eager = y.cpu().numpy()
+    ref1 = oc.conv2d(x, w1, b1, 1, 1, True)
+    a1h = a1.cpu().numpy()
+    assert np.all(np.abs(a1h - ref1) <= _tol(WINO, x, w1, b1, ref1, c1))
+    p1h = oc.maxpool2x2(a1h)
+    ref2 = oc.conv2d(p1h.reshape(1, 1, 1, -1), w2, b2, 1, 0, False)
+    assert np.all(np.abs(eager - ref2) <= _tol(IM2COL, p1h, w2, b2, ref2, fc))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        net(dx, torch.cuda.current_stream())
+    other = torch.from_numpy(_data(1, 16, 16, 8, 32, 3, 3, seed=93)[0]).cuda()
+    for _ in range(3):
+        net(other, torch.cuda.current_stream())     # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), eager)
