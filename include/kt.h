@@ -149,7 +149,7 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
  * beta == 0).  Arguments and layouts as kt_gemm; 0 <= splits <= 64.
  * splits == 0 chooses S: the configuration is config_id, or the selector's
  * pick for the whole product, and S doubles from 1 while that configuration
- * fills fewer than 512 work-groups (tiles x batch x S), each slice stays at
+ * fills fewer than 2048 work-groups (tiles x batch x S), each slice stays at
  * least 256 deep and S < 64.  When S == 1 (also splits == 1 or K <= 64)
  * this is exactly kt_gemm and needs no workspace.  *used_splits (host, may
  * be NULL) receives S.  The workspace
@@ -163,7 +163,7 @@ kt_status kt_gemm_splitk(kt_handle h, kt_dtype in_dtype, const kt_shape* s, int3
                          int32_t* used_splits);
 /* Workspace bytes of kt_gemm_splitk: splits * batch * M * N floats, rounded
  * up to 256 bytes (0 for splits == 1); for splits == 0 a bound that covers
- * every automatic choice, min(64 * batch * M * N, 2^26) floats.  Host only. */
+ * every automatic choice, min(64 * batch * M * N, 2^28) floats.  Host only. */
 kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size_t* bytes);
 
 /* ------------------------------------------------------------ convolution */

@@ -34,12 +34,16 @@ size_t plane_bytes(const kt_shape* s) { return (size_t)s->batch * s->M * s->N * 
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Automatic slice count: double S while the launch has fewer than 512
-// work-groups (two per compute unit), the slices stay at least 256 deep and
-// S < 64.  Hence S * tiles < 1024, which bounds the workspace (below).
+// Automatic slice count: double S while the launch has fewer than
+// AUTO_WG_TARGET work-groups (eight per compute unit: the products this is
+// for are skinny and mostly wait on memory, so they want many loads in
+// flight), the slices stay at least 256 deep and S < 64.  Hence
+// S * tiles < 2 * AUTO_WG_TARGET, which bounds the workspace (below).
+constexpr int64_t AUTO_WG_TARGET = 2048;
+
 int32_t auto_splits(int64_t tiles, int64_t K) {
   int32_t S = 1;
-  while (tiles * S < 512 && S < SPLITK_MAX && K / (2 * S) >= 256) S *= 2;
+  while (tiles * S < AUTO_WG_TARGET && S < SPLITK_MAX && K / (2 * S) >= 256) S *= 2;
   return S;
 }
 
@@ -83,8 +87,8 @@ kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size
   if (splits < 0 || splits > SPLITK_MAX) return fail(nullptr, KT_EINVAL, "need 0 <= splits <= 64");
   if (s->M < 0 || s->N < 0 || s->K < 0 || s->batch < 0)
     return fail(nullptr, KT_EINVAL, "negative M, N, K or batch");
-  if (splits == 0) {   // automatic: S * plane <= S * tiles * tile area < 1024 * MAX_TILE_AREA
-    const size_t cap = (size_t)1024 * MAX_TILE_AREA * 4;
+  if (splits == 0) {   // automatic: S * plane <= S * tiles * tile area < 2 * target * MAX_TILE_AREA
+    const size_t cap = (size_t)(2 * AUTO_WG_TARGET) * MAX_TILE_AREA * 4;
     const size_t all = (size_t)SPLITK_MAX * plane_bytes(s);
     *bytes = a256(all < cap ? all : cap);
     return KT_OK;

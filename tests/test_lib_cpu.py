@@ -107,9 +107,9 @@ def test_splitk_workspace_query_and_host_handle(kt):
     for bad in (65, -2):
         with pytest.raises(kt.KtError):
             kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, bad)
-    # automatic (0): bounded by 64 planes and by 1024 tiles of the largest area
+    # automatic (0): bounded by 64 planes and by 4096 tiles of the largest area
     assert kt.Handle.splitk_workspace_bytes(100, 70, 5000, 3, 0) == -(-64 * 3 * 100 * 70 * 4 // 256) * 256
-    assert kt.Handle.splitk_workspace_bytes(4096, 4096, 5000, 1, 0) == 1024 * 256 * 256 * 4
+    assert kt.Handle.splitk_workspace_bytes(4096, 4096, 5000, 1, 0) == 4096 * 256 * 256 * 4
     h = kt.Handle(-1)
     s = kt.shape(8, 8, 512)
     st = h.L.kt_gemm_splitk(h.h, 0, ctypes.byref(s), 4, 1.0, None, 512, 0, None, 8, 0, 0.0, None, 8,

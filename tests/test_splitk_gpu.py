@@ -194,7 +194,7 @@ def test_splitk_low_precision(gpu, dtype, ta, tb):
 
 def _auto_splits(tiles, K):
     S = 1
-    while tiles * S < 512 and S < 64 and K // (2 * S) >= 256:
+    while tiles * S < 2048 and S < 64 and K // (2 * S) >= 256:
         S *= 2
     return S
 
@@ -202,7 +202,7 @@ def _auto_splits(tiles, K):
 @pytest.mark.parametrize("M,N,K,bt", [(1, 4096, 25088, 1), (1, 1000, 4096, 1), (300, 200, 900, 2),
                                       (2000, 2000, 3000, 1)])
 def test_splitk_automatic(gpu, M, N, K, bt):
-    """splits = 0: S doubles while the configuration fills fewer than 512
+    """splits = 0: S doubles while the configuration fills fewer than 2048
     work-groups and slices stay >= 256 deep (S < 64); results as in FP32
     parity."""
     h, torch = gpu
