@@ -563,7 +563,7 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
 def conv_section(kt, h, tune, problems_conv_path, sel_kinds, fit_args):
     """Held-out generalization: the GEMMs of a VGG16-style conv stack (im2col
     and Winograd lowerings, never seen in training) through the selectors
-    fitted on the sweep set, judged against their own exhaustive sweep."""
+    fitted on the sweep set, measured against their own exhaustive sweep."""
     if not os.path.exists(problems_conv_path):
         return None
     TC, PC, CC, metaC = tune.load_table(problems_conv_path)

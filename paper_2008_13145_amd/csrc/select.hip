@@ -6,7 +6,7 @@
 // paper's nested if statements in the kernel launcher -- to pick one of the
 // deployed configurations.  Exhaustive search (time every compiled
 // configuration once per unseen shape, then cache) is the fallback selector
-// and the judge of a selector's regret.
+// and the reference that a selector's regret is measured against.
 //
 // Integer CART: features (M, N, K, batch, transA, transB) as raw integers;
 // Gini criterion with splits scored by S = A/n_L + B/n_R (A, B the sums of
