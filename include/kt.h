@@ -180,7 +180,13 @@ kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size
  * (KT_EUNSUPPORTED otherwise); input and filter transforms in the workspace,
  * 16 GEMMs of T x Cin by Cin x Cout in one batched launch (T = n ceil(Ho/2)
  * ceil(Wo/2) tiles), output transform with bias and activation fused. */
-typedef enum { KT_CONV_IM2COL = 0, KT_CONV_WINOGRAD = 1 } kt_conv_algo;
+typedef enum {
+  KT_CONV_IM2COL = 0,
+  KT_CONV_WINOGRAD = 1,
+  /* Winograd with w holding the 16 x Cin x Cout transformed filter written
+   * by kt_winograd_filter (weights transformed once, when they are loaded) */
+  KT_CONV_WINOGRAD_PRETRANSFORMED = 2
+} kt_conv_algo;
 
 typedef struct {
   int64_t n, H, W, Cin, Cout;
@@ -209,6 +215,12 @@ kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, i
 kt_status kt_conv2d(kt_handle h, kt_conv_algo algo, const kt_conv_shape* c, const float* x,
                     const float* w, const float* bias, int32_t relu, float* y, int32_t config_id,
                     int32_t splits, void* workspace, size_t ws_bytes, void* stream);
+/* The Winograd F(2x2, 3x3) filter transform U[k][c][o] = (G g Gt)[k] of the
+ * 3x3 filters g = w[:, :, c, o] (device arrays: w is (3, 3, Cin, Cout), U is
+ * 16 x Cin x Cout floats), for KT_CONV_WINOGRAD_PRETRANSFORMED.
+ * Asynchronous on `stream`. */
+kt_status kt_winograd_filter(kt_handle h, const float* w, int64_t Cin, int64_t Cout, float* U,
+                             void* stream);
 /* 2x2 max pooling with stride 2 on NHWC FP32 (device): y is
  * (n, H/2, W/2, C); an odd trailing row or column is dropped. */
 kt_status kt_maxpool2x2(kt_handle h, const float* x, int64_t n, int64_t H, int64_t W, int64_t C,

@@ -60,7 +60,7 @@ class ConvShape(ctypes.Structure):
                 ("R", c_i32), ("S", c_i32), ("stride", c_i32), ("pad", c_i32)]
 
 
-CONV_IM2COL, CONV_WINOGRAD = 0, 1
+CONV_IM2COL, CONV_WINOGRAD, CONV_WINOGRAD_PRETRANSFORMED = 0, 1, 2
 
 
 def conv_shape(n, H, W, Cin, Cout, R=3, S=3, stride=1, pad=1) -> ConvShape:
@@ -93,6 +93,7 @@ _SIGS = {
                                           ctypes.POINTER(c_sz)]),
     "kt_conv2d": (c_i32, [c_vp, c_i32, ctypes.POINTER(ConvShape), c_vp, c_vp, c_vp, c_i32, c_vp,
                           c_i32, c_i32, c_vp, c_sz, c_vp]),
+    "kt_winograd_filter": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
     "kt_maxpool2x2": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp]),
     "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
     "kt_convert_bf16": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
@@ -337,6 +338,10 @@ class Handle:
                                      _ptr(bias), int(bool(relu)), _ptr(y), int(config_id),
                                      int(splits), _ptr(workspace), int(ws_bytes),
                                      _stream(stream)))
+
+    def winograd_filter(self, w, Cin, Cout, U, stream=None):
+        self._check(self.L.kt_winograd_filter(self.h, _ptr(w), int(Cin), int(Cout), _ptr(U),
+                                              _stream(stream)))
 
     def maxpool2x2(self, x, n, H, W, C, y, stream=None):
         self._check(self.L.kt_maxpool2x2(self.h, _ptr(x), int(n), int(H), int(W), int(C), _ptr(y),

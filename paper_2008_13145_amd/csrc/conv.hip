@@ -198,12 +198,13 @@ maxpool2x2_kernel(const float* __restrict__ x, int64_t n, int64_t H, int64_t W, 
 
 kt_status check_conv(Ctx* h, kt_conv_algo algo, const kt_conv_shape* c, ConvDims* d) {
   if (!c) return fail(h, KT_EINVAL, "conv shape is NULL");
-  if (algo != KT_CONV_IM2COL && algo != KT_CONV_WINOGRAD) return fail(h, KT_EINVAL, "bad algorithm");
+  if (algo != KT_CONV_IM2COL && algo != KT_CONV_WINOGRAD && algo != KT_CONV_WINOGRAD_PRETRANSFORMED)
+    return fail(h, KT_EINVAL, "bad algorithm");
   if (c->n < 0 || c->H < 0 || c->W < 0 || c->Cin < 1 || c->Cout < 1)
     return fail(h, KT_EINVAL, "need n, H, W >= 0 and Cin, Cout >= 1");
   if (c->R < 1 || c->S < 1 || c->stride < 1 || c->pad < 0)
     return fail(h, KT_EINVAL, "need R, S, stride >= 1 and pad >= 0");
-  if (algo == KT_CONV_WINOGRAD && (c->R != 3 || c->S != 3 || c->stride != 1))
+  if (algo != KT_CONV_IM2COL && (c->R != 3 || c->S != 3 || c->stride != 1))
     return fail(h, KT_EUNSUPPORTED, "Winograd F(2x2,3x3) needs a 3x3 filter and stride 1");
   d->n = c->n; d->H = c->H; d->W = c->W; d->C = c->Cin; d->O = c->Cout;
   d->R = c->R; d->S = c->S; d->st = c->stride; d->pad = c->pad;
@@ -236,13 +237,13 @@ size_t conv_main_bytes(const ConvDims& d, kt_conv_algo algo) {
   kt_shape s;
   conv_gemm_shape(d, algo, &s);
   if (algo == KT_CONV_IM2COL) return pointwise(d) ? 0 : a256((size_t)s.M * s.K * 4);
-  return a256((size_t)16 * s.M * d.C * 4) + a256((size_t)16 * d.C * d.O * 4) +
-         a256((size_t)16 * s.M * d.O * 4);
+  const size_t u = algo == KT_CONV_WINOGRAD ? a256((size_t)16 * d.C * d.O * 4) : 0;
+  return a256((size_t)16 * s.M * d.C * 4) + u + a256((size_t)16 * s.M * d.O * 4);
 }
 
 kt_status check_splits(Ctx* h, kt_conv_algo algo, int32_t splits) {
   if (splits < 0 || splits > 64) return fail(h, KT_EINVAL, "need 0 <= splits <= 64");
-  if (algo == KT_CONV_WINOGRAD && splits > 1)
+  if (algo != KT_CONV_IM2COL && splits > 1)
     return fail(h, KT_EUNSUPPORTED, "split-K is offered for the im2col lowering only");
   return KT_OK;
 }
@@ -340,15 +341,19 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
   int32_t cfg = config_id;
   if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
   const int64_t tH = (d.Ho + 1) / 2, tW = (d.Wo + 1) / 2, T = gs.M;
+  const bool pre = algo == KT_CONV_WINOGRAD_PRETRANSFORMED;   // w already holds U
   float* V = (float*)ws;
-  float* U = (float*)(ws + a256((size_t)16 * T * d.C * 4));
-  float* Mm = (float*)((char*)U + a256((size_t)16 * d.C * d.O * 4));
+  char* after_v = ws + a256((size_t)16 * T * d.C * 4);
+  const float* U = pre ? w : (const float*)after_v;
+  float* Mm = (float*)(pre ? after_v : after_v + a256((size_t)16 * d.C * d.O * 4));
   hipLaunchKernelGGL(wino_input_kernel, dim3(grid_for(cdiv(T * d.C, CT))), dim3(CT), 0, s, x, d,
                      tH, tW, V);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "Winograd input launch");
-  hipLaunchKernelGGL(wino_filter_kernel, dim3(grid_for(cdiv(d.C * d.O, CT))), dim3(CT), 0, s, w,
-                     d.C, d.O, U);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "Winograd filter launch");
+  if (!pre) {
+    hipLaunchKernelGGL(wino_filter_kernel, dim3(grid_for(cdiv(d.C * d.O, CT))), dim3(CT), 0, s, w,
+                       d.C, d.O, (float*)after_v);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "Winograd filter launch");
+  }
   // M[k] (T x O) = V[k] (T x C) * U[k] (C x O), k = 0..15
   st = launch_gemm(h, KT_F32, &gs, 1.f, V, d.C, T * d.C, U, d.O, d.C * d.O, 0.f, Mm, d.O, T * d.O,
                    nullptr, nullptr, cfg, s);
@@ -356,6 +361,20 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
   hipLaunchKernelGGL(wino_output_kernel, dim3(grid_for(cdiv(T * d.O, CT))), dim3(CT), 0, s, Mm, d,
                      tH, tW, bias, relu, y);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "Winograd output launch");
+  return KT_OK;
+}
+
+kt_status kt_winograd_filter(kt_handle hh, const float* w, int64_t Cin, int64_t Cout, float* U,
+                             void* stream) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!need_device(h)) return KT_EINVAL;
+  if (Cin < 1 || Cout < 1) return fail(h, KT_EINVAL, "need Cin, Cout >= 1");
+  if (!w || !U) return fail(h, KT_EINVAL, "w or U is NULL");
+  hipLaunchKernelGGL(wino_filter_kernel, dim3(grid_for(cdiv(Cin * Cout, CT))), dim3(CT), 0,
+                     (hipStream_t)stream, w, Cin, Cout, U);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "Winograd filter launch");
   return KT_OK;
 }
 

@@ -252,3 +252,32 @@ def test_graph_captured_stack_matches_eager(gpu):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), eager)
+
+
+@pytest.mark.parametrize("case", [(1, 14, 14, 64, 128, 1), (2, 7, 9, 32, 48, 0)])
+def test_winograd_pretransformed_filters(gpu, case):
+    """Filters transformed once (kt_winograd_filter) and passed to the
+    pre-transformed Winograd path give the same bits as the Winograd path
+    that transforms them itself, within the oracle bound."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    n, H, W, C, O, pad = case
+    cs = kt.conv_shape(n, H, W, C, O, 3, 3, 1, pad)
+    x, w, b = _data(n, H, W, C, O, 3, 3, seed=950 + sum(case))
+    cfg = h.configs().index((64, 64, 4, 16))
+    plain = _run(h, torch, WINO, cs, x, w, b, True, cfg)
+    dw = torch.from_numpy(w).cuda()
+    U = torch.full((16 * C * O,), float("nan"), device="cuda")
+    h.winograd_filter(dw, C, O, U)
+    ws_bytes = kt.Handle.conv_workspace_bytes(cs, kt.CONV_WINOGRAD_PRETRANSFORMED)
+    assert ws_bytes < kt.Handle.conv_workspace_bytes(cs, WINO)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    Ho, Wo = H + 2 * pad - 2, W + 2 * pad - 2
+    dy = torch.full((n, Ho, Wo, O), float("nan"), device="cuda")
+    h.conv2d(kt.CONV_WINOGRAD_PRETRANSFORMED, cs, torch.from_numpy(x).cuda(), U,
+             torch.from_numpy(b).cuda(), True, dy, ws, ws_bytes, config_id=cfg)
+    torch.cuda.synchronize()
+    got = dy.cpu().numpy()
+    assert np.array_equal(got, plain)
+    ref = oc.conv2d(x, w, b, 1, pad, True)
+    assert np.all(np.abs(got - ref) <= _tol(WINO, x, w, b, ref, cs))
