@@ -319,6 +319,7 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
       col = (const float*)ws;
     }
     // y (P x O) = col (P x RSC) * w (RSC x O)
+    bool fused = false;   // bias and activation applied by the split-K reduction
     if (splits == 1) {
       int32_t cfg = config_id;
       if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
@@ -326,12 +327,12 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
                        d.O, gs.M * d.O, nullptr, nullptr, cfg, s);
     } else {
       const size_t main = conv_main_bytes(d, algo);
-      st = kt_gemm_splitk(hh, KT_F32, &gs, splits, 1.f, col, gs.K, gs.M * gs.K, w, d.O,
-                          gs.K * d.O, 0.f, y, d.O, gs.M * d.O, nullptr, nullptr, config_id,
-                          ws + main, ws_bytes - main, stream, nullptr);
+      st = splitk_gemm(h, KT_F32, &gs, splits, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O,
+                       0.f, y, d.O, gs.M * d.O, nullptr, nullptr, config_id, ws + main,
+                       ws_bytes - main, stream, nullptr, bias, relu, &fused);
     }
     if (st != KT_OK) return st;
-    if (bias || relu) {
+    if ((bias || relu) && !fused) {
       hipLaunchKernelGGL(bias_act_kernel, dim3(grid_for(cdiv(gs.M * d.O, CT))), dim3(CT), 0, s, y,
                          gs.M, d.O, bias, relu);
       if ((e = hipGetLastError()) != hipSuccess) return hip_fail(h, e, "bias launch");

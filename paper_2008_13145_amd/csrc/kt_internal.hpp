@@ -97,4 +97,14 @@ const std::vector<uint16_t>& sigmoid_table(Ctx* h);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// kt_gemm_splitk with an optional per-column bias and ReLU applied by the
+// reduction pass; *epilogue_done reports whether that pass ran (with a single
+// slice the plain GEMM runs and the caller applies bias and activation).
+kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits, float alpha,
+                      const void* A, int64_t lda, int64_t strideA, const void* B, int64_t ldb,
+                      int64_t strideB, float beta, float* C, int64_t ldc, int64_t strideC,
+                      const float* scaleA, const float* scaleB, int32_t config_id,
+                      void* workspace, size_t ws_bytes, void* stream, int32_t* used_splits,
+                      const float* bias, int32_t relu, bool* epilogue_done);
+
 }  // namespace kt

@@ -51,12 +51,14 @@ int32_t auto_splits(int64_t tiles, int64_t K) {
 constexpr int64_t MAX_TILE_AREA = 256 * 256;
 
 // C[b][i][j] = alpha * sum_s W[s][b][i][j] + beta * C[b][i][j]; C is not
-// read when beta is 0.  Each work-group covers RED_THREADS consecutive
-// columns of one output row, so plane reads and C accesses are coalesced.
+// read when beta is 0.  An optional per-column bias (added after alpha and
+// beta) and ReLU serve the convolution layers.  Each work-group covers
+// RED_THREADS consecutive columns of one output row, so plane reads and C
+// accesses are coalesced.
 __global__ void __launch_bounds__(RED_THREADS)
 splitk_reduce_kernel(const float* __restrict__ W, int32_t S, int64_t plane, int64_t M, int64_t N,
                      int64_t rows, float alpha, float beta, float* __restrict__ C, int64_t ldc,
-                     int64_t sC) {
+                     int64_t sC, const float* __restrict__ bias, int32_t relu) {
   const int64_t col_blocks = (N + RED_THREADS - 1) / RED_THREADS;
   const int64_t total = rows * col_blocks;
   for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
@@ -70,7 +72,8 @@ splitk_reduce_kernel(const float* __restrict__ W, int32_t S, int64_t plane, int6
     float* c = C + b * sC + i * ldc + j;
     float out = alpha * acc;
     if (beta != 0.f) out = fmaf(beta, *c, out);
-    *c = out;
+    if (bias) out += bias[j];
+    *c = relu ? fmaxf(out, 0.f) : out;
   }
 }
 
@@ -103,7 +106,22 @@ kt_status kt_gemm_splitk(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_
                          int64_t strideC, const float* scaleA, const float* scaleB,
                          int32_t config_id, void* workspace, size_t ws_bytes, void* stream,
                          int32_t* used_splits) {
-  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  return kt::splitk_gemm(reinterpret_cast<Ctx*>(hh), dtype, s, splits, alpha, A, lda, strideA, B,
+                         ldb, strideB, beta, C, ldc, strideC, scaleA, scaleB, config_id,
+                         workspace, ws_bytes, stream, used_splits, nullptr, 0, nullptr);
+}
+
+}  // extern "C"
+
+namespace kt {
+
+kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits, float alpha,
+                      const void* A, int64_t lda, int64_t strideA, const void* B, int64_t ldb,
+                      int64_t strideB, float beta, float* C, int64_t ldc, int64_t strideC,
+                      const float* scaleA, const float* scaleB, int32_t config_id,
+                      void* workspace, size_t ws_bytes, void* stream, int32_t* used_splits,
+                      const float* bias, int32_t relu, bool* epilogue_done) {
+  if (epilogue_done) *epilogue_done = false;
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!need_device(h)) return KT_EINVAL;
   if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
@@ -182,11 +200,12 @@ kt_status kt_gemm_splitk(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_
   const int64_t blocks = rows * cdiv(s->N, RED_THREADS);
   const unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid), dim3(RED_THREADS), 0, stream_h, W, S, plane,
-                     s->M, s->N, rows, alpha, beta, C, ldc, strideC);
+                     s->M, s->N, rows, alpha, beta, C, ldc, strideC, bias, relu);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "split-K reduction launch");
   if (used_splits) *used_splits = S;
+  if (epilogue_done) *epilogue_done = true;
   return KT_OK;
 }
 
-}  // extern "C"
+}  // namespace kt
