@@ -13,6 +13,11 @@ libraries", arXiv 2008.13145) and says which:
 * ``normalize``  -- section 3.4: relative, raw-cutoff, standard-cutoff and
                     sigmoid normalization of one problem's performance vector.
 * ``kmeans``     -- section 4.1 (k-means) and 4.2 (centroid -> kernel, Top-N).
+* ``pca``        -- section 4.1 (PCA before k-means) and the pruning built on it.
+* ``represent``  -- section 4.2: a cluster's kernel from a representative or
+                    from the geometric mean of its members.
+* ``prune_tree`` -- section 4.1: decision-tree pruning to k leaves.
+* ``conv``       -- section 6: direct convolution and pooling (VGG16 layers).
 * ``cart``       -- section 5.1: decision-tree classifiers A/B/C.
 * ``regret``     -- section 4.3: fraction of optimal performance, geometric mean.
 * ``mlp``        -- the MLP cost model that stands in for the decision tree

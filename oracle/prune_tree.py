@@ -106,6 +106,16 @@ def fit(F, X, k: int):
     return nodes, pre
 
 
+def leaf_labels(F, X, k: int):
+    """(labels, n_leaves): the pre-order position of the leaf each row
+    reaches, for the representative rules of ``oracle.represent``."""
+    nodes, pre = fit(F, X, k)
+    labels = np.zeros(len(X), dtype=np.int64)
+    for pos, leaf in enumerate(pre):
+        labels[nodes[leaf]["rows"]] = pos
+    return labels, len(pre)
+
+
 def prune(F, X, k: int):
     """The k configurations chosen by decision-tree pruning."""
     X = np.asarray(X, dtype=np.int64)
