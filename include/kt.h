@@ -336,6 +336,108 @@ kt_status kt_kmeans_u16(kt_handle h, const uint16_t* X, int32_t n, int32_t d, in
 kt_status kt_prune_tree(kt_handle h, const kt_shape* shapes, const uint16_t* Xq, int32_t n,
                         int32_t d, int32_t k, int32_t* chosen);
 
+/* The same decision-tree pruning as kt_prune_tree, returning the leaves
+ * instead of the picks: labels[i] (host, n) = pre-order position of the leaf
+ * row i reaches, *n_leaves = number of leaves (<= k).  Feeding the labels to
+ * kt_representatives(KT_REP_MEAN) gives kt_prune_tree's picks;
+ * KT_REP_GEOMEAN gives the paper's rule for label-only clusters.  Host only,
+ * limits as kt_prune_tree. */
+kt_status kt_prune_tree_leaves(kt_handle h, const kt_shape* shapes, const uint16_t* Xq, int32_t n,
+                               int32_t d, int32_t k, int32_t* labels, int32_t* n_leaves);
+
+/* ------------------------------------------- clusters -> kernels (4.2) */
+
+/* How a cluster becomes the kernel to deploy (section 4.2).  A clustering
+ * that yields a representative deploys the configuration best for it; one
+ * that yields only labels deploys the configuration best for the geometric
+ * mean of the members. */
+typedef enum {
+  KT_REP_MEAN = 0,      /* rounded member mean floor((2 s + n) / (2 n)): the k-means centroid */
+  KT_REP_GEOMEAN = 1,   /* geometric mean of the members' Q16 values, 0 counted as 1 / 65535 */
+  KT_REP_CENTROID = 2   /* PCA pruning only: the k-means centroid read back through the
+                           components as Q16 values of every configuration */
+} kt_rep;
+
+/* One configuration per cluster from labels (host arrays: Xq n x d Q16
+ * rows, labels[n] in 0..n_clusters-1).  Clusters in label order each take
+ * their best configuration not already taken (lowest index on ties); empty
+ * clusters take nothing; a short list is completed with the unpicked
+ * configurations of largest column sum over all rows (of the values for
+ * KT_REP_MEAN, of their logarithms for KT_REP_GEOMEAN).  KT_REP_GEOMEAN
+ * compares products through the fixed-point logarithm of
+ * kt_log2_q16_table, summed exactly in int64.  chosen[k] (host) receives the
+ * picks.  Host only (works on a handle without a device); n <= 2^26. */
+kt_status kt_representatives(kt_handle h, const uint16_t* Xq, int32_t n, int32_t d,
+                             const int32_t* labels, int32_t n_clusters, int32_t k, kt_rep rep,
+                             int32_t* chosen);
+/* table[q] = round(2^32 * log2(max(q, 1) / 65535)) for q = 0..65535 (host,
+ * 65536 int64): the logarithm KT_REP_GEOMEAN sums. */
+kt_status kt_log2_q16_table(int64_t* table);
+
+/* Principal components of the rows x = q / 65535 of a Q16 table (section
+ * 4.1, PCA before k-means; host, FP64): centred at the column means,
+ * covariance Xc^T Xc / (n - 1), unit eigenvectors by decreasing eigenvalue
+ * (cyclic Jacobi), each signed so that its first entry within a factor
+ * 1 - 1e-9 of its largest magnitude is positive.  Optional host outputs:
+ * mean[d], components[m][d] (the first m), variances[d] (every eigenvalue,
+ * decreasing), U[n][m] = rint((Z - lo) / span * 65535) with Z = Xc V_m and
+ * one offset lo = min Z and scale span = max Z - lo for every coordinate
+ * (U = 0 when span = 0), lo_span[2] = {lo, span}, *explained = the first m
+ * eigenvalues' share of the trace.  Needs n >= 2, 1 <= m <= d <= 1024. */
+kt_status kt_pca(kt_handle h, const uint16_t* Xq, int32_t n, int32_t d, int32_t m, double* mean,
+                 double* components, double* variances, uint16_t* U, double* lo_span,
+                 double* explained);
+
+/* PCA + k-means pruning (section 4.1): normalize the host time table on the
+ * GPU (kt_normalize), project the rows on their first m principal
+ * components and quantize them (kt_pca), cluster with the integer k-means of
+ * kt_kmeans_u16 (same seed, restarts and limits), and take one kernel per
+ * cluster: KT_REP_CENTROID reads each centroid c back as the point
+ * mean + V_m (lo + c span / 65535) and takes its largest Q16 value
+ * rint(65535 x); KT_REP_GEOMEAN applies kt_representatives to the labels on
+ * the normalized table.  Picks are distinct, in cluster order.  Workspace:
+ * kt_prune_workspace_bytes(n_rows, n_configs, k, n_init).  Outputs (host):
+ * chosen[k], *inertia_out (of the quantized k-means), optionally
+ * labels[n_rows] and *explained.  Synchronizes `stream`. */
+kt_status kt_prune_pca(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                       int32_t k, kt_norm norm, int32_t m, kt_rep rep, uint64_t seed,
+                       int32_t n_init, int32_t max_iter, void* workspace, size_t ws_bytes,
+                       void* stream, int32_t* chosen, int64_t* inertia_out, int32_t* labels,
+                       double* explained);
+
+/* k-means pruning (kt_prune) under each normalization of section 3.4,
+ * keeping the one whose chosen set scores best on the same rows by the
+ * paper's measure (kt_evaluate's geometric-mean ceiling; ties keep the
+ * earlier normalization).  chosen[k], *norm_out and, if not NULL,
+ * scores[4] (the ceiling of each normalization) are host outputs.
+ * Workspace as kt_prune.  Synchronizes `stream`. */
+kt_status kt_prune_auto(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                        int32_t k, uint64_t seed, int32_t n_init, int32_t max_iter,
+                        void* workspace, size_t ws_bytes, void* stream, int32_t* chosen,
+                        int32_t* norm_out, double* scores);
+
+/* ------------------------------------------------------ evaluation (4.3) */
+
+typedef struct {
+  double geomean;       /* geometric mean of r = t_best / t_used: the paper's figure */
+  double mean, min;
+  double frac_ge_0_9;   /* share of rows with r >= 0.9 */
+  double time_weighted; /* sum t_best / sum t_used */
+  int32_t n;
+} kt_eval;
+
+/* Fraction of the optimal performance a selection keeps (section 4.3), on
+ * a host time table [n_rows][n_configs] (t <= 0: unmeasured).  Evaluated rows:
+ * rows[n_eval] (host), or every row when rows is NULL.  t_best is the row's
+ * smallest measured time over all configurations; t_used is the time of
+ * picks[e] for the e-th evaluated row when picks (host) is not NULL (a
+ * selector's choice), else the smallest measured time among chosen[k] (the
+ * ceiling of a pruned set).  KT_EINVAL when a row has no measured t_best or
+ * t_used.  Host only. */
+kt_status kt_evaluate(kt_handle h, const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                      const int32_t* rows, int32_t n_eval, const int32_t* picks,
+                      const int32_t* chosen, int32_t k, kt_eval* out);
+
 /* Top-N baseline of section 4.2: the k configurations that are best (largest
  * relative value, lowest index on ties) for the most rows, ties in the count
  * to the lower index.  time_ns and chosen are host arrays; the workspace is
@@ -374,11 +476,41 @@ kt_status kt_fit_selector(kt_handle h, kt_dtype dtype, kt_selector sel, const kt
                           const int32_t* chosen, int32_t k, const kt_mlp_opts* mlp,
                           void* workspace, size_t ws_bytes, void* stream);
 
+/* Fit the selector of section 5.1 that generalizes best: decision trees A,
+ * B, C and the MLP cost model are each fitted on the rows with
+ * is_validation[i] == 0 (host array, n_rows) and scored on the others by the
+ * geometric mean of t_best / t_picked (section 4.3; t_best over all
+ * configurations of the row, the model's own pick without the fallback
+ * below); the best (earliest kind on ties) is then refitted on all rows and
+ * kept.  *kind_out receives it, scores[4] (optional, host) every kind's
+ * validation score (0 for the MLP on a handle without a device, which
+ * cannot train it).  Other arguments as kt_fit_selector. */
+kt_status kt_fit_selector_validated(kt_handle h, kt_dtype dtype, const kt_shape* shapes,
+                                    const int64_t* time_ns, int32_t n_rows, int32_t n_configs,
+                                    const int32_t* chosen, int32_t k, const uint8_t* is_validation,
+                                    const kt_mlp_opts* mlp, void* workspace, size_t ws_bytes,
+                                    void* stream, int32_t* kind_out, double* scores);
+
 /* Configuration id for a shape (host).  KT_ENOTFITTED before a fit or load,
  * except for KT_SEL_EXHAUSTIVE, which times every compiled configuration for
  * an unseen shape once (on scratch buffers the handle allocates) and caches
- * the winner. */
+ * the winner.  Fallback (decision trees and MLP, on by default): a shape
+ * whose M, N, K or batch lies outside the range the selector was fitted on
+ * is not given to the model; the chosen configurations are timed on it once
+ * (scratch as above, synchronizing) and the fastest is cached for the
+ * shape. */
 kt_status kt_select(kt_handle h, kt_dtype dtype, const kt_shape* s, int32_t* config_id);
+
+/* Turn the out-of-range fallback of kt_select on (1) or off (0) for the
+ * selector of a dtype (kept across refits; saved by kt_save). */
+kt_status kt_set_fallback(kt_handle h, kt_dtype dtype, int32_t enabled);
+
+/* The fitted selector of a dtype (host outputs, each optional): *kind
+ * (kt_selector, -1 = none), *k and chosen[k] (pass NULL to query k first),
+ * box[8] = the smallest then the largest M, N, K, batch it was fitted on
+ * (0 ... -1 when unknown), *fallback. */
+kt_status kt_selector_info(kt_handle h, kt_dtype dtype, int32_t* kind, int32_t* k,
+                           int32_t* chosen, int64_t* box, int32_t* fallback);
 
 /* Same for n shapes on the device: d_shapes and d_ids are device arrays. */
 kt_status kt_select_batch(kt_handle h, kt_dtype dtype, const kt_shape* d_shapes, int32_t n,

@@ -12,7 +12,9 @@ Readings (the paper leaves these open):
 
 * clusters are taken in label order 0..n_clusters-1; each picks its best
   configuration not already picked (lowest index on ties), so the picks are
-  distinct; an empty cluster picks nothing; when fewer than k picks result,
+  distinct, and picking stops once k are taken (a clustering with more
+  clusters than k deploys its first k); an empty cluster picks nothing;
+  when fewer than k picks result,
   the rest are the unpicked configurations with the largest column sums
   over all rows (of the values for the mean rule, of their logarithms for
   the geometric-mean rule), lowest index on ties;
@@ -46,6 +48,8 @@ def pick_distinct(scores, k: int, fill_scores=None):
     best unpicked j per cluster in order, then fill from fill_scores."""
     picked = []
     for sc in scores:
+        if len(picked) == k:
+            break
         if sc is None:
             continue
         order = sorted(range(len(sc)), key=lambda j: (-int(sc[j]), j))

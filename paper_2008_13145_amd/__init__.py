@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("KT_LIBRARY", os.path.join(HERE, "libkt.so"))
 
 F32, BF16, FP8E4M3 = 0, 1, 2
 NORM_RELATIVE, NORM_RAWCUT, NORM_STDCUT, NORM_SIGMOID = 0, 1, 2, 3
+REP_MEAN, REP_GEOMEAN, REP_CENTROID = 0, 1, 2
 SEL_DT_A, SEL_DT_B, SEL_DT_C, SEL_MLP, SEL_EXHAUSTIVE = 0, 1, 2, 3, 4
 
 STATUS = {0: "KT_OK", -1: "KT_EINVAL", -2: "KT_EUNSUPPORTED", -3: "KT_EHIP",
@@ -48,6 +49,11 @@ class SweepOpts(ctypes.Structure):
 class MlpOpts(ctypes.Structure):
     _fields_ = [("steps", c_i32), ("lr", c_f32), ("init", ctypes.POINTER(c_f32)), ("seed", c_u64),
                 ("graph_steps", c_i32)]
+
+
+class Eval(ctypes.Structure):
+    _fields_ = [("geomean", ctypes.c_double), ("mean", ctypes.c_double), ("min", ctypes.c_double),
+                ("frac_ge_0_9", ctypes.c_double), ("time_weighted", ctypes.c_double), ("n", c_i32)]
 
 
 class GroupedOpts(ctypes.Structure):
@@ -105,12 +111,29 @@ _SIGS = {
     "kt_prune_workspace_bytes": (c_i32, [c_i32, c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_prune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                          c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
+    "kt_prune_tree_leaves": (c_i32, [c_vp, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_i32, c_vp,
+                                     ctypes.POINTER(c_i32)]),
+    "kt_representatives": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp]),
+    "kt_log2_q16_table": (c_i32, [c_vp]),
+    "kt_pca": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "kt_prune_pca": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_u64, c_i32,
+                             c_i32, c_vp, c_sz, c_vp, c_vp, ctypes.POINTER(c_i64), c_vp, c_vp]),
+    "kt_prune_auto": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz, c_vp,
+                              c_vp, ctypes.POINTER(c_i32), c_vp]),
+    "kt_evaluate": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_i32,
+                            ctypes.POINTER(Eval)]),
     "kt_prune_topn": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_sz, c_vp, c_vp]),
     "kt_prune_tree": (c_i32, [c_vp, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_i32, c_vp]),
     "kt_kmeans_u16": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_u64, c_i32, c_i32, c_vp, c_sz,
                               c_vp, c_vp, c_vp, ctypes.POINTER(c_i64)]),
     "kt_fit_selector": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32, c_vp,
                                 c_i32, ctypes.POINTER(MlpOpts), c_vp, c_sz, c_vp]),
+    "kt_fit_selector_validated": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i32, c_i32,
+                                          c_vp, c_i32, c_vp, ctypes.POINTER(MlpOpts), c_vp, c_sz,
+                                          c_vp, ctypes.POINTER(c_i32), c_vp]),
+    "kt_set_fallback": (c_i32, [c_vp, c_i32, c_i32]),
+    "kt_selector_info": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), c_vp,
+                                 c_vp, ctypes.POINTER(c_i32)]),
     "kt_select": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), ctypes.POINTER(c_i32)]),
     "kt_select_batch": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_vp, c_vp]),
     "kt_get_tree": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32), c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -435,6 +458,100 @@ class Handle:
         self._check(self.L.kt_prune_tree(self.h, arr, Xq.ctypes.data, n, d, int(k), out.ctypes.data))
         return [int(v) for v in out]
 
+    def prune_tree_leaves(self, shapes, Xq, k):
+        """Leaf (pre-order position) of every row under decision-tree pruning;
+        returns (labels, n_leaves)."""
+        Xq = np.ascontiguousarray(np.asarray(Xq).astype(np.uint16))
+        n, d = Xq.shape
+        labels = np.zeros(n, dtype=np.int32)
+        nl = c_i32()
+        self._check(self.L.kt_prune_tree_leaves(self.h, shapes_array(shapes), Xq.ctypes.data, n, d,
+                                                int(k), labels.ctypes.data, ctypes.byref(nl)))
+        return labels, nl.value
+
+    def representatives(self, Xq, labels, n_clusters, k, rep=REP_MEAN):
+        """One configuration per cluster (section 4.2) from labels on a Q16 table."""
+        Xq = np.ascontiguousarray(np.asarray(Xq).astype(np.uint16))
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        out = np.zeros(k, dtype=np.int32)
+        self._check(self.L.kt_representatives(self.h, Xq.ctypes.data, Xq.shape[0], Xq.shape[1],
+                                              lab.ctypes.data, int(n_clusters), int(k), int(rep),
+                                              out.ctypes.data))
+        return [int(v) for v in out]
+
+    @staticmethod
+    def log2_q16_table():
+        t = np.zeros(65536, dtype=np.int64)
+        st = lib().kt_log2_q16_table(t.ctypes.data)
+        if st != 0:
+            raise KtError(st, "log table")
+        return t
+
+    def pca(self, Xq, m):
+        """Principal components of a Q16 table: dict(mean, components,
+        variances, U, lo, span, explained)."""
+        Xq = np.ascontiguousarray(np.asarray(Xq).astype(np.uint16))
+        n, d = Xq.shape
+        mean = np.zeros(d)
+        comps = np.zeros((m, d))
+        var = np.zeros(d)
+        U = np.zeros((n, m), dtype=np.uint16)
+        ls = np.zeros(2)
+        ex = ctypes.c_double()
+        self._check(self.L.kt_pca(self.h, Xq.ctypes.data, n, d, int(m), mean.ctypes.data,
+                                  comps.ctypes.data, var.ctypes.data, U.ctypes.data, ls.ctypes.data,
+                                  ctypes.byref(ex)))
+        return dict(mean=mean, components=comps, variances=var, U=U, lo=float(ls[0]),
+                    span=float(ls[1]), explained=ex.value)
+
+    def prune_pca(self, time_ns, k, norm, m, rep=REP_CENTROID, seed=13145, n_init=10,
+                  max_iter=300, workspace=None, ws_bytes=0, stream=None):
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        n, d = T.shape
+        chosen = np.zeros(k, dtype=np.int32)
+        labels = np.zeros(n, dtype=np.int32)
+        inertia = c_i64()
+        ex = ctypes.c_double()
+        self._check(self.L.kt_prune_pca(self.h, T.ctypes.data, n, d, int(k), int(norm), int(m),
+                                        int(rep), int(seed) & (2 ** 64 - 1), int(n_init),
+                                        int(max_iter), _ptr(workspace), int(ws_bytes),
+                                        _stream(stream), chosen.ctypes.data, ctypes.byref(inertia),
+                                        labels.ctypes.data, ctypes.byref(ex)))
+        return dict(chosen=[int(c) for c in chosen], labels=labels, inertia=inertia.value,
+                    explained=ex.value)
+
+    def prune_auto(self, time_ns, k, seed=13145, n_init=10, max_iter=300, workspace=None,
+                   ws_bytes=0, stream=None):
+        """k-means pruning under the normalization whose chosen set keeps the
+        most of the optimum on these rows: dict(chosen, norm, scores)."""
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        n, d = T.shape
+        chosen = np.zeros(k, dtype=np.int32)
+        norm = c_i32()
+        scores = np.zeros(4)
+        self._check(self.L.kt_prune_auto(self.h, T.ctypes.data, n, d, int(k),
+                                         int(seed) & (2 ** 64 - 1), int(n_init), int(max_iter),
+                                         _ptr(workspace), int(ws_bytes), _stream(stream),
+                                         chosen.ctypes.data, ctypes.byref(norm), scores.ctypes.data))
+        return dict(chosen=[int(c) for c in chosen], norm=norm.value, scores=scores.tolist())
+
+    def evaluate(self, time_ns, rows=None, picks=None, chosen=None):
+        """Fraction-of-optimal summary (section 4.3): a selector's picks per
+        evaluated row, or the ceiling of a chosen set; returns a dict."""
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+        p = None if picks is None else np.ascontiguousarray(picks, dtype=np.int32)
+        c = None if chosen is None else np.ascontiguousarray(chosen, dtype=np.int32)
+        out = Eval()
+        self._check(self.L.kt_evaluate(self.h, T.ctypes.data, T.shape[0], T.shape[1],
+                                       None if r is None else r.ctypes.data,
+                                       0 if r is None else len(r),
+                                       None if p is None else p.ctypes.data,
+                                       None if c is None else c.ctypes.data,
+                                       0 if c is None else len(c), ctypes.byref(out)))
+        return dict(geomean=out.geomean, mean=out.mean, min=out.min, frac_ge_0_9=out.frac_ge_0_9,
+                    time_weighted=out.time_weighted, n=out.n)
+
     def kmeans_u16(self, X, k, seed=13145, n_init=10, max_iter=300, workspace=None, ws_bytes=0,
                    stream=None):
         """k-means on arbitrary 16-bit vectors (host array n x d)."""
@@ -469,6 +586,40 @@ class Handle:
                                            None if opts is None else ctypes.byref(opts),
                                            _ptr(workspace), int(ws_bytes), _stream(stream)))
         del keep
+
+    def fit_selector_validated(self, shapes, time_ns, chosen, is_validation, mlp_steps=3000,
+                               mlp_lr=1e-3, mlp_seed=13150, mlp_graph_steps=25, workspace=None,
+                               ws_bytes=0, stream=None, dtype=F32):
+        """Fit trees A/B/C and the MLP on the non-validation rows, keep the
+        kind that scores best on the validation rows, refit it on all rows.
+        Returns (kind, [score per kind])."""
+        arr = shapes_array(shapes)
+        T = np.ascontiguousarray(time_ns, dtype=np.int64)
+        ch = np.ascontiguousarray(chosen, dtype=np.int32)
+        val = np.ascontiguousarray(np.asarray(is_validation, dtype=bool).astype(np.uint8))
+        assert len(val) == T.shape[0]
+        opts = MlpOpts(int(mlp_steps), float(mlp_lr), None, int(mlp_seed), int(mlp_graph_steps))
+        kind = c_i32()
+        scores = np.zeros(4)
+        self._check(self.L.kt_fit_selector_validated(
+            self.h, int(dtype), arr, T.ctypes.data, T.shape[0], T.shape[1], ch.ctypes.data, len(ch),
+            val.ctypes.data, ctypes.byref(opts), _ptr(workspace), int(ws_bytes), _stream(stream),
+            ctypes.byref(kind), scores.ctypes.data))
+        return kind.value, scores.tolist()
+
+    def set_fallback(self, enabled, dtype=F32):
+        self._check(self.L.kt_set_fallback(self.h, int(dtype), int(bool(enabled))))
+
+    def selector_info(self, dtype=F32):
+        kind, k, fb = c_i32(), c_i32(), c_i32()
+        self._check(self.L.kt_selector_info(self.h, int(dtype), ctypes.byref(kind), ctypes.byref(k),
+                                            None, None, None))
+        ch = np.zeros(max(k.value, 1), dtype=np.int32)
+        box = np.zeros(8, dtype=np.int64)
+        self._check(self.L.kt_selector_info(self.h, int(dtype), ctypes.byref(kind), ctypes.byref(k),
+                                            ch.ctypes.data, box.ctypes.data, ctypes.byref(fb)))
+        return dict(kind=kind.value, chosen=ch[:k.value].tolist(), box_lo=box[:4].tolist(),
+                    box_hi=box[4:].tolist(), fallback=fb.value)
 
     def select(self, M, N, K, batch=1, transA=0, transB=0, dtype=F32) -> int:
         v = c_i32()

@@ -52,9 +52,37 @@ def _compile(src, obj, verbose):
     return obj
 
 
+def _local_includes(path, seen):
+    """Files reached through #include "..." from path (searched next to the
+    including file, then in csrc/ and include/)."""
+    import re
+    for line in open(path):
+        m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+        if not m:
+            continue
+        for base in (os.path.dirname(path), CSRC, INCLUDE):
+            cand = os.path.normpath(os.path.join(base, m.group(1)))
+            if os.path.exists(cand):
+                if cand not in seen:
+                    seen.add(cand)
+                    _local_includes(cand, seen)
+                break
+    return seen
+
+
+def _up_to_date(src, obj):
+    """True when obj is newer than its source and every header it includes."""
+    if not os.path.exists(obj):
+        return False
+    deps = [src] + sorted(_local_includes(src, set()))
+    return os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps)
+
+
 def build(jobs: int | None = None, f32_ids=None, lp_ids=None, out: str = LIB,
-          verbose: bool = False, tag: str = "full") -> str:
-    """Compile and link; returns the path of the shared library."""
+          verbose: bool = False, tag: str = "full", incremental: bool = False) -> str:
+    """Compile and link; returns the path of the shared library.  With
+    incremental=True, objects newer than their source and every header are
+    reused (a development shortcut; the default recompiles everything)."""
     from . import codegen
     bdir = os.path.join(HERE, "_build", tag)
     gdir = os.path.join(bdir, "gen")
@@ -65,8 +93,9 @@ def build(jobs: int | None = None, f32_ids=None, lp_ids=None, out: str = LIB,
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = [os.path.join(odir, os.path.basename(s) + ".o") for s in srcs]
     t0 = time.time()
+    todo = [(so, o) for so, o in zip(srcs, objs) if not (incremental and _up_to_date(so, o))]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(srcs, objs)))
+        list(ex.map(lambda so: _compile(so[0], so[1], verbose), todo))
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp] + objs
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -97,11 +126,13 @@ def main(argv=None):
     ap.add_argument("--ids", type=str, default=None, help="comma-separated FP32 config ids (deploy build)")
     ap.add_argument("--out", type=str, default=None)
     ap.add_argument("--deploy", action="store_true", help="also build the recorded deploy library")
+    ap.add_argument("--incremental", action="store_true",
+                    help="reuse objects newer than their sources and headers")
     a = ap.parse_args(argv)
     ids = None if a.ids is None else [int(x) for x in a.ids.split(",") if x]
     out = a.out or (LIB if ids is None else os.path.join(HERE, "libkt_deploy.so"))
     build(jobs=a.jobs, f32_ids=ids, lp_ids=None if ids is None else [], out=out, verbose=True,
-          tag="full" if ids is None else "deploy")
+          tag="full" if ids is None else "deploy", incremental=a.incremental)
     if a.deploy and ids is None:
         build_deploy(jobs=a.jobs, verbose=True)
 

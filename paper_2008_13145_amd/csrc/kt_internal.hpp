@@ -45,6 +45,13 @@ struct SelState {
   size_t d_tree_bytes = 0;
   void* d_mlp = nullptr;           // device copy of the MLP weights + chosen ids
   std::map<ShapeKey, int32_t> exhaustive_cache;
+  // Training box of a fitted model: the smallest and largest M, N, K and
+  // batch it was fitted on.  Shapes outside it are timed over the chosen
+  // configurations instead of trusting the model (when fallback is on).
+  bool have_box = false;
+  int64_t box_lo[4] = {0, 0, 0, 0}, box_hi[4] = {0, 0, 0, 0};
+  int32_t fallback = 1;
+  std::map<ShapeKey, int32_t> fallback_cache;
 };
 
 struct Ctx {
@@ -91,6 +98,12 @@ kt_status fit_mlp(Ctx* h, int dtype, const kt_shape* shapes, const int64_t* time
                   int32_t d, const int32_t* chosen, int32_t k, const kt_mlp_opts* o, void* ws,
                   size_t ws_bytes, hipStream_t st);
 void free_selector_device(Ctx* h, int dtype);
+
+// Normalize a host time table on the GPU (workspace of
+// kt_prune_workspace_bytes(n, d, 1, 1) or more) and copy the Q16 result to
+// host memory; synchronizes the stream.
+kt_status normalize_table_host(Ctx* h, const int64_t* time_ns, int32_t n, int32_t d, kt_norm norm,
+                               void* workspace, size_t ws_bytes, hipStream_t st, uint16_t* out);
 
 // Sigmoid lookup table of the normalization (Q16 -> Q16).
 const std::vector<uint16_t>& sigmoid_table(Ctx* h);

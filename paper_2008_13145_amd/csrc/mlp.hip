@@ -44,13 +44,65 @@ struct MlpLayout {
   }
 };
 
-__device__ __forceinline__ void shape_features(const kt_shape& s, float* x) {
-  x[0] = log2f((float)s.M) * (1.0f / 12.0f);
-  x[1] = log2f((float)s.N) * (1.0f / 12.0f);
-  x[2] = log2f((float)s.K) * (1.0f / 12.0f);
-  x[3] = log2f((float)s.batch) * (1.0f / 6.0f);
+// log2 of a positive integer, evaluated by the same float operations on the
+// host and on the device so that host and device selection agree bit for bit
+// (the math libraries' log2f may differ in the last place): v = m 2^e with
+// e = floor(log2 v) and m in [1, 2] (float(v) scaled exactly by 2^-e), then
+// log2 m = (2 / ln 2) atanh(t), t = (m - 1) / (m + 1) in [0, 1/3], from the
+// odd series t (1 + t^2/3 + ... + t^14/15) (truncation below 5e-10), in
+// Horner form with explicit fused multiply-adds.  Values <= 1 give 0.
+__host__ __device__ inline float feature_log2(int64_t v) {
+  if (v <= 1) return 0.f;
+  const int e = 63 - __builtin_clzll((unsigned long long)v);
+  const float m = ldexpf((float)v, -e);
+  const float t = (m - 1.f) / (m + 1.f);
+  const float t2 = t * t;
+  float p = 1.f / 15.f;
+  p = fmaf(p, t2, 1.f / 13.f);
+  p = fmaf(p, t2, 1.f / 11.f);
+  p = fmaf(p, t2, 1.f / 9.f);
+  p = fmaf(p, t2, 1.f / 7.f);
+  p = fmaf(p, t2, 1.f / 5.f);
+  p = fmaf(p, t2, 1.f / 3.f);
+  p = fmaf(p, t2, 1.f);
+  const float u = 2.88539008f * t;   // 2 / ln 2
+  return fmaf(u, p, (float)e);
+}
+
+__host__ __device__ inline void shape_features(const kt_shape& s, float* x) {
+  x[0] = feature_log2(s.M) * (1.0f / 12.0f);
+  x[1] = feature_log2(s.N) * (1.0f / 12.0f);
+  x[2] = feature_log2(s.K) * (1.0f / 12.0f);
+  x[3] = feature_log2(s.batch) * (1.0f / 6.0f);
   x[4] = (float)s.transA;
   x[5] = (float)s.transB;
+}
+
+// Features -> forward -> argmax (lowest index on ties): the position in the
+// chosen list.  Shared by the batch selection kernel and the host launcher
+// path, with the same operation order, so both pick the same kernel.
+__host__ __device__ inline int mlp_forward_argmax(const kt_shape& shape, const float* P, int k) {
+  const MlpLayout L(k);
+  float x[MLP_IN], h1[MLP_H], h2[MLP_H];
+  shape_features(shape, x);
+  for (int o = 0; o < MLP_H; ++o) {
+    float s = P[L.ob1 + o];
+    for (int q = 0; q < MLP_IN; ++q) s = fmaf(x[q], P[L.oW1 + o * MLP_IN + q], s);
+    h1[o] = fmaxf(s, 0.f);
+  }
+  for (int o = 0; o < MLP_H; ++o) {
+    float s = P[L.ob2 + o];
+    for (int q = 0; q < MLP_H; ++q) s = fmaf(h1[q], P[L.oW2 + o * MLP_H + q], s);
+    h2[o] = fmaxf(s, 0.f);
+  }
+  int best = 0;
+  float bv = 0.f;
+  for (int o = 0; o < k; ++o) {
+    float s = P[L.ob3 + o];
+    for (int q = 0; q < MLP_H; ++q) s = fmaf(h2[q], P[L.oW3 + o * MLP_H + q], s);
+    if (o == 0 || s > bv) { bv = s; best = o; }
+  }
+  return best;
 }
 
 __global__ void mlp_features_kernel(const kt_shape* __restrict__ shapes, int n, float* __restrict__ X) {
@@ -242,27 +294,7 @@ __global__ void mlp_select_kernel(const kt_shape* __restrict__ shapes, int n, co
                                   int k, const int32_t* __restrict__ chosen, int32_t* __restrict__ ids) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const MlpLayout L(k);
-  float x[MLP_IN], h1[MLP_H], h2[MLP_H];
-  shape_features(shapes[i], x);
-  for (int o = 0; o < MLP_H; ++o) {
-    float s = P[L.ob1 + o];
-    for (int q = 0; q < MLP_IN; ++q) s = fmaf(x[q], P[L.oW1 + o * MLP_IN + q], s);
-    h1[o] = fmaxf(s, 0.f);
-  }
-  for (int o = 0; o < MLP_H; ++o) {
-    float s = P[L.ob2 + o];
-    for (int q = 0; q < MLP_H; ++q) s = fmaf(h1[q], P[L.oW2 + o * MLP_H + q], s);
-    h2[o] = fmaxf(s, 0.f);
-  }
-  int best = 0;
-  float bv = 0.f;
-  for (int o = 0; o < k; ++o) {
-    float s = P[L.ob3 + o];
-    for (int q = 0; q < MLP_H; ++q) s = fmaf(h2[q], P[L.oW3 + o * MLP_H + q], s);
-    if (o == 0 || s > bv) { bv = s; best = o; }
-  }
-  ids[i] = chosen[best];
+  ids[i] = chosen[mlp_forward_argmax(shapes[i], P, k)];
 }
 
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -367,19 +399,13 @@ kt_status mlp_select_batch(Ctx* h, int dtype, const kt_shape* d_shapes, int32_t 
   return KT_OK;
 }
 
+// Host selection: the same forward pass on the host copy of the weights, so
+// kt_gemm(config_id = -1) with the MLP selector makes no device call besides
+// the GEMM launch itself (no copy, no synchronization, capturable in a graph).
 kt_status mlp_select_host(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
-  SelState& S = h->sel[dtype];
-  if (!need_device(h)) return KT_EINVAL;
-  if (!S.d_mlp) return fail(h, KT_ENOTFITTED, "MLP weights not on the device");
-  // a 64-byte staging area past the chosen ids holds the shape and the answer
-  char* base = (char*)S.d_mlp + S.mlp.params.size() * 4 + S.chosen.size() * 4;
-  base = (char*)(((uintptr_t)base + 15) & ~(uintptr_t)15);
-  hipError_t e = hipMemcpy(base, s, sizeof(kt_shape), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(h, e, "upload shape");
-  kt_status r = mlp_select_batch(h, dtype, (const kt_shape*)base, 1, (int32_t*)(base + 64), nullptr);
-  if (r != KT_OK) return r;
-  e = hipMemcpy(id, base + 64, 4, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(h, e, "read selection");
+  const SelState& S = h->sel[dtype];
+  if (S.mlp.params.empty() || S.mlp.k < 1) return fail(h, KT_ENOTFITTED, "no MLP weights");
+  *id = S.chosen[mlp_forward_argmax(*s, S.mlp.params.data(), S.mlp.k)];
   return KT_OK;
 }
 

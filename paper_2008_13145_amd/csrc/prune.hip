@@ -364,6 +364,23 @@ static kt_status ensure_lut(Ctx* h, hipStream_t st) {
   return KT_OK;
 }
 
+kt_status normalize_table_host(Ctx* h, const int64_t* time_ns, int32_t n, int32_t d, kt_norm norm,
+                               void* workspace, size_t ws_bytes, hipStream_t st, uint16_t* out) {
+  if (!need_device(h)) return KT_EINVAL;
+  kt_status s = check_table(h, n, d);
+  if (s != KT_OK) return s;
+  if ((int)norm < 0 || (int)norm > 3) return fail(h, KT_EINVAL, "bad normalization");
+  const PrunePlan p = prune_plan(n, d, 1, 1);
+  if (!workspace || ws_bytes < p.total) return fail(h, KT_EWORKSPACE, "normalization workspace too small");
+  s = upload_normalize(h, time_ns, n, d, norm, (char*)workspace, p, st);
+  if (s != KT_OK) return s;
+  hipError_t e = hipMemcpyAsync(out, (char*)workspace + p.off_X, (size_t)n * d * 2,
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(h, e, "read normalized table");
+  return KT_OK;
+}
+
 }  // namespace kt
 
 using namespace kt;

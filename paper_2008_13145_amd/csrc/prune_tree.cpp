@@ -106,19 +106,11 @@ struct RegTree {
   }
 };
 
-}  // namespace
-
-}  // namespace kt
-
-using namespace kt;
-
-extern "C" {
-
-kt_status kt_prune_tree(kt_handle hh, const kt_shape* shapes, const uint16_t* Xq, int32_t n,
-                        int32_t d, int32_t k, int32_t* chosen) {
-  Ctx* h = reinterpret_cast<Ctx*>(hh);
-  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
-  if (!shapes || !Xq || !chosen) return fail(h, KT_EINVAL, "NULL argument");
+// Grow the regression tree best first to at most k leaves; returns the
+// nodes and the leaves in pre-order (left child first).
+kt_status grow_tree(Ctx* h, const kt_shape* shapes, const uint16_t* Xq, int32_t n, int32_t d,
+                    int32_t k, std::vector<Node>& nodes, std::vector<int>& pre) {
+  if (!shapes || !Xq) return fail(h, KT_EINVAL, "NULL argument");
   if (n < 1 || d < 1 || k < 1 || k > d) return fail(h, KT_EINVAL, "need n, d >= 1 and 1 <= k <= d");
   if (n > TREE_MAX_ROWS || d > TREE_MAX_D)
     return fail(h, KT_EUNSUPPORTED, "decision-tree pruning limits: n <= 4096, d <= 256");
@@ -132,7 +124,7 @@ kt_status kt_prune_tree(kt_handle hh, const kt_shape* shapes, const uint16_t* Xq
     }
   }
   RegTree tr{F.data(), Xq, d};
-  std::vector<Node> nodes(1);
+  nodes.assign(1, Node());
   nodes[0].rows.resize(n);
   std::iota(nodes[0].rows.begin(), nodes[0].rows.end(), 0);
   std::vector<Split> cand(1, tr.best_split(nodes[0].rows));
@@ -162,8 +154,8 @@ kt_status kt_prune_tree(kt_handle hh, const kt_shape* shapes, const uint16_t* Xq
     leaves.push_back((int)nodes.size() - 2);
     leaves.push_back((int)nodes.size() - 1);
   }
-  // leaves in pre-order, each picks its rounded-mean argmax (distinct)
-  std::vector<int> pre, stack(1, 0);
+  pre.clear();
+  std::vector<int> stack(1, 0);
   while (!stack.empty()) {
     const int i = stack.back();
     stack.pop_back();
@@ -171,6 +163,42 @@ kt_status kt_prune_tree(kt_handle hh, const kt_shape* shapes, const uint16_t* Xq
     stack.push_back(nodes[i].right);
     stack.push_back(nodes[i].left);
   }
+  return KT_OK;
+}
+
+}  // namespace
+
+}  // namespace kt
+
+using namespace kt;
+
+extern "C" {
+
+kt_status kt_prune_tree_leaves(kt_handle hh, const kt_shape* shapes, const uint16_t* Xq, int32_t n,
+                               int32_t d, int32_t k, int32_t* labels, int32_t* n_leaves) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!labels || !n_leaves) return fail(h, KT_EINVAL, "NULL argument");
+  std::vector<Node> nodes;
+  std::vector<int> pre;
+  kt_status st = grow_tree(h, shapes, Xq, n, d, k, nodes, pre);
+  if (st != KT_OK) return st;
+  for (size_t pos = 0; pos < pre.size(); ++pos)
+    for (int32_t i : nodes[pre[pos]].rows) labels[i] = (int32_t)pos;
+  *n_leaves = (int32_t)pre.size();
+  return KT_OK;
+}
+
+kt_status kt_prune_tree(kt_handle hh, const kt_shape* shapes, const uint16_t* Xq, int32_t n,
+                        int32_t d, int32_t k, int32_t* chosen) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!chosen) return fail(h, KT_EINVAL, "NULL argument");
+  std::vector<Node> nodes;
+  std::vector<int> pre;
+  kt_status st = grow_tree(h, shapes, Xq, n, d, k, nodes, pre);
+  if (st != KT_OK) return st;
+  // leaves in pre-order, each picks its rounded-mean argmax (distinct)
   std::vector<char> used(d, 0);
   int32_t m = 0;
   std::vector<int64_t> s(d);

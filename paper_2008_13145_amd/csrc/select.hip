@@ -193,14 +193,12 @@ static kt_status upload_tree(Ctx* h, int dtype) {
 
 static int64_t elem_bytes_sel(int dtype) { return dtype == KT_F32 ? 4 : dtype == KT_BF16 ? 2 : 1; }
 
-// Exhaustive selection: time every compiled configuration of the shape's
-// layout on handle-owned scratch operands (generated in FP32 and converted
-// for BF16 / FP8); the fastest (lowest id on ties) is cached for the shape.
-static kt_status exhaustive_select(Ctx* h, int dtype, const kt_shape* s, int32_t* out) {
-  SelState& S = h->sel[dtype];
-  const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, dtype};
-  auto it = S.exhaustive_cache.find(key);
-  if (it != S.exhaustive_cache.end()) { *out = it->second; return KT_OK; }
+// Time the candidate configurations (those compiled for the shape's layout)
+// on handle-owned scratch operands (generated in FP32 and converted for
+// BF16 / FP8): one untimed launch, then three timed ones each; the fastest
+// (first on ties) wins.  Allocates the scratch on first use and synchronizes.
+static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
+                                 const std::vector<int32_t>& cands, int32_t* out) {
   if (!need_device(h)) return KT_EINVAL;
   const int64_t eb = elem_bytes_sel(dtype);
   const int64_t a_rows = s->transA ? s->K : s->M, a_cols = s->transA ? s->M : s->K;
@@ -250,7 +248,8 @@ static kt_status exhaustive_select(Ctx* h, int dtype, const kt_shape* s, int32_t
   int32_t best = -1;
   float best_ms = 0.f;
   kt_status st = KT_OK;
-  for (int32_t id = 0; id < (int32_t)h->configs[dtype].size() && st == KT_OK; ++id) {
+  for (size_t ci = 0; ci < cands.size() && st == KT_OK; ++ci) {
+    const int32_t id = cands[ci];
     if (!find_launcher(h, dtype, id, s->transA, s->transB)) continue;
     auto launch = [&]() {
       return launch_gemm(h, dtype, s, 1.f, A, lda, a_rows * lda, B, ldb, b_rows * ldb, 0.f, C, ldc,
@@ -268,13 +267,58 @@ static kt_status exhaustive_select(Ctx* h, int dtype, const kt_shape* s, int32_t
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != KT_OK) return st;
-  if (best < 0) return fail(h, KT_EUNSUPPORTED, "no configuration compiled for this layout");
-  S.exhaustive_cache[key] = best;
+  if (best < 0) return fail(h, KT_EUNSUPPORTED, "no candidate configuration compiled for this layout");
   *out = best;
   return KT_OK;
 }
 
-kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
+// Exhaustive selection: every configuration of the dtype, cached per shape.
+static kt_status exhaustive_select(Ctx* h, int dtype, const kt_shape* s, int32_t* out) {
+  SelState& S = h->sel[dtype];
+  const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, dtype};
+  auto it = S.exhaustive_cache.find(key);
+  if (it != S.exhaustive_cache.end()) { *out = it->second; return KT_OK; }
+  std::vector<int32_t> all(h->configs[dtype].size());
+  std::iota(all.begin(), all.end(), 0);
+  kt_status st = time_candidates(h, dtype, s, all, out);
+  if (st == KT_OK) S.exhaustive_cache[key] = *out;
+  return st;
+}
+
+static bool outside_box(const SelState& S, const kt_shape& s) {
+  const int64_t v[4] = {s.M, s.N, s.K, s.batch};
+  for (int f = 0; f < 4; ++f)
+    if (v[f] < S.box_lo[f] || v[f] > S.box_hi[f]) return true;
+  return false;
+}
+
+static void set_box(SelState& S, const kt_shape* shapes, int32_t n) {
+  S.have_box = n > 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t v[4] = {shapes[i].M, shapes[i].N, shapes[i].K, shapes[i].batch};
+    for (int f = 0; f < 4; ++f) {
+      if (i == 0 || v[f] < S.box_lo[f]) S.box_lo[f] = v[f];
+      if (i == 0 || v[f] > S.box_hi[f]) S.box_hi[f] = v[f];
+    }
+  }
+}
+
+// Fallback for a shape outside the training box: the fastest of the chosen
+// configurations, timed once and cached.
+static kt_status fallback_select(Ctx* h, int dtype, const kt_shape* s, int32_t* out) {
+  SelState& S = h->sel[dtype];
+  const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, dtype};
+  auto it = S.fallback_cache.find(key);
+  if (it != S.fallback_cache.end()) { *out = it->second; return KT_OK; }
+  kt_status st = time_candidates(h, dtype, s, S.chosen, out);
+  if (st == KT_OK) S.fallback_cache[key] = *out;
+  return st;
+}
+
+
+
+// The fitted model's pick, never the fallback.
+static kt_status model_select(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
   SelState& S = h->sel[dtype];
   switch (S.kind) {
     case KT_SEL_DT_A:
@@ -291,6 +335,16 @@ kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
     default:
       return fail(h, KT_ENOTFITTED, "no selector fitted or loaded for this dtype");
   }
+}
+
+kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
+  const SelState& S = h->sel[dtype];
+  // Outside the training box the model is extrapolating: time the chosen
+  // configurations once instead.
+  if (S.kind >= KT_SEL_DT_A && S.kind <= KT_SEL_MLP && S.fallback && S.have_box &&
+      outside_box(S, *s) && h->device >= 0)
+    return fallback_select(h, dtype, s, id);
+  return model_select(h, dtype, s, id);
 }
 
 static bool bad_dtype(int d) { return d < 0 || d >= NUM_DTYPES; }
@@ -324,13 +378,16 @@ kt_status kt_fit_selector(kt_handle hh, kt_dtype dtype, kt_selector sel, const k
     for (int32_t q = 0; q < j; ++q)
       if (chosen[q] == chosen[j]) return fail(h, KT_EINVAL, "chosen ids must be distinct");
   }
+  const int32_t keep_fallback = S.fallback;
   if (sel == KT_SEL_MLP) {
     kt_status st = fit_mlp(h, dtype, shapes, time_ns, n, d, chosen, k, mlp, ws, ws_bytes,
                            (hipStream_t)stream);
     if (st != KT_OK) return st;
+    S.fallback = keep_fallback;
     S.kind = KT_SEL_MLP;
     S.tree = Tree();
     S.exhaustive_cache.clear();
+    set_box(S, shapes, n);
     return KT_OK;
   }
   CartData D;
@@ -361,6 +418,8 @@ kt_status kt_fit_selector(kt_handle hh, kt_dtype dtype, kt_selector sel, const k
   S.tree = std::move(T);
   S.chosen.assign(chosen, chosen + k);
   S.kind = sel;
+  S.fallback = keep_fallback;
+  set_box(S, shapes, n);
   return upload_tree(h, dtype);
 }
 
@@ -418,14 +477,16 @@ kt_status kt_get_tree(kt_handle hh, kt_dtype dtype, int32_t* n_nodes, int32_t* f
   return KT_OK;
 }
 
-// Text format (version 2):
-//   KTSEL 2
+// Text format (version 3; version 2 files, without the box line, load with
+// no training box):
+//   KTSEL 3
 //   selectors <count>
 //   then per selector:
 //     dtype <d> kind <k>
 //     chosen <k> id...
 //     tree <n>        followed by n lines: feature threshold left right cls
 //     mlp <count>     followed by count floats in %a notation
+//     box <have> <fallback> lo_M lo_N lo_K lo_batch hi_M hi_N hi_K hi_batch
 //   end
 kt_status kt_save(kt_handle hh, const char* path) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
@@ -436,7 +497,7 @@ kt_status kt_save(kt_handle hh, const char* path) {
   if (count == 0) return fail(h, KT_ENOTFITTED, "nothing to save");
   FILE* f = fopen(path, "w");
   if (!f) return fail(h, KT_EIO, std::string("cannot write ") + path);
-  fprintf(f, "KTSEL 2\nselectors %d\n", count);
+  fprintf(f, "KTSEL 3\nselectors %d\n", count);
   for (int d = 0; d < NUM_DTYPES; ++d) {
     const SelState& S = h->sel[d];
     if (S.kind < 0) continue;
@@ -448,6 +509,10 @@ kt_status kt_save(kt_handle hh, const char* path) {
               S.tree.left[i], S.tree.right[i], S.tree.cls[i]);
     fprintf(f, "mlp %zu\n", S.mlp.params.size());
     for (float v : S.mlp.params) fprintf(f, "%a\n", (double)v);
+    fprintf(f, "box %d %d", S.have_box ? 1 : 0, S.fallback);
+    for (int q = 0; q < 4; ++q) fprintf(f, " %lld", (long long)S.box_lo[q]);
+    for (int q = 0; q < 4; ++q) fprintf(f, " %lld", (long long)S.box_hi[q]);
+    fprintf(f, "\n");
   }
   fprintf(f, "end\n");
   const bool ok = fflush(f) == 0 && !ferror(f);
@@ -465,9 +530,16 @@ kt_status kt_load(kt_handle hh, const char* path) {
   auto bad = [&](const char* why) { return fail(h, KT_EIO, std::string("malformed selector file: ") + why); };
   std::string tag;
   int ver = 0, count = 0;
-  if (!(in >> tag >> ver) || tag != "KTSEL" || ver != 2) return bad("header");
+  if (!(in >> tag >> ver) || tag != "KTSEL" || (ver != 2 && ver != 3)) return bad("header");
   if (!(in >> tag >> count) || tag != "selectors" || count < 1 || count > NUM_DTYPES) return bad("selector count");
-  struct Loaded { int dtype, kind; std::vector<int32_t> chosen; Tree tree; std::vector<float> params; };
+  struct Loaded {
+    int dtype, kind;
+    std::vector<int32_t> chosen;
+    Tree tree;
+    std::vector<float> params;
+    int have_box = 0, fallback = 1;
+    long long lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+  };
   std::vector<Loaded> all;
   for (int q = 0; q < count; ++q) {
     Loaded L;
@@ -505,6 +577,13 @@ kt_status kt_load(kt_handle hh, const char* path) {
       if (!endp || *endp) return bad("mlp value");
       L.params[i] = (float)v;
     }
+    if (ver >= 3) {
+      if (!(in >> tag >> L.have_box >> L.fallback) || tag != "box" || (L.have_box & ~1) ||
+          (L.fallback & ~1))
+        return bad("box");
+      for (int q = 0; q < 4; ++q) if (!(in >> L.lo[q])) return bad("box bounds");
+      for (int q = 0; q < 4; ++q) if (!(in >> L.hi[q])) return bad("box bounds");
+    }
     if (L.kind <= KT_SEL_DT_C && (nn == 0 || k == 0)) return bad("tree selector without nodes");
     if (L.kind == KT_SEL_MLP && np != (size_t)64 * 6 + 64 + 64 * 64 + 64 + k * 64 + k) return bad("mlp size");
     all.push_back(std::move(L));
@@ -519,12 +598,94 @@ kt_status kt_load(kt_handle hh, const char* path) {
     S.tree = std::move(L.tree);
     S.mlp.k = (int32_t)L.chosen.size();
     S.mlp.params = std::move(L.params);
+    S.have_box = L.have_box != 0;
+    S.fallback = L.fallback;
+    for (int q = 0; q < 4; ++q) { S.box_lo[q] = L.lo[q]; S.box_hi[q] = L.hi[q]; }
     kt_status st = KT_OK;
     if (S.kind <= KT_SEL_DT_C) st = upload_tree(h, L.dtype);
     else if (S.kind == KT_SEL_MLP) st = mlp_upload(h, L.dtype);
     if (st != KT_OK) return st;
   }
   return KT_OK;
+}
+
+kt_status kt_set_fallback(kt_handle hh, kt_dtype dtype, int32_t enabled) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
+  if (enabled != 0 && enabled != 1) return fail(h, KT_EINVAL, "enabled must be 0 or 1");
+  h->sel[dtype].fallback = enabled;
+  return KT_OK;
+}
+
+kt_status kt_selector_info(kt_handle hh, kt_dtype dtype, int32_t* kind, int32_t* k,
+                           int32_t* chosen, int64_t* box, int32_t* fallback) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
+  const SelState& S = h->sel[dtype];
+  if (kind) *kind = S.kind;
+  if (k) *k = (int32_t)S.chosen.size();
+  if (chosen) memcpy(chosen, S.chosen.data(), S.chosen.size() * 4);
+  if (box) {
+    for (int q = 0; q < 4; ++q) { box[q] = S.have_box ? S.box_lo[q] : 0; box[4 + q] = S.have_box ? S.box_hi[q] : -1; }
+  }
+  if (fallback) *fallback = S.fallback;
+  return KT_OK;
+}
+
+kt_status kt_fit_selector_validated(kt_handle hh, kt_dtype dtype, const kt_shape* shapes,
+                                    const int64_t* time_ns, int32_t n, int32_t d,
+                                    const int32_t* chosen, int32_t k, const uint8_t* is_validation,
+                                    const kt_mlp_opts* mlp, void* ws, size_t ws_bytes, void* stream,
+                                    int32_t* kind_out, double* scores) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
+  if (!shapes || !time_ns || !chosen || !is_validation || !kind_out)
+    return fail(h, KT_EINVAL, "NULL argument");
+  if (n < 2 || d < 1) return fail(h, KT_EINVAL, "bad training data");
+  std::vector<kt_shape> fit_s, val_s;
+  std::vector<int64_t> fit_t, val_t;
+  for (int32_t i = 0; i < n; ++i) {
+    const bool v = is_validation[i] != 0;
+    (v ? val_s : fit_s).push_back(shapes[i]);
+    std::vector<int64_t>& t = v ? val_t : fit_t;
+    t.insert(t.end(), time_ns + (size_t)i * d, time_ns + (size_t)(i + 1) * d);
+  }
+  if (fit_s.empty() || val_s.empty())
+    return fail(h, KT_EINVAL, "need at least one fitting row and one validation row");
+  const int32_t nv = (int32_t)val_s.size();
+  double best = -1.0;
+  int32_t best_kind = -1;
+  std::vector<int32_t> picks(nv);
+  for (int kind = KT_SEL_DT_A; kind <= KT_SEL_MLP; ++kind) {
+    if (kind == KT_SEL_MLP && h->device < 0) {   // a host handle cannot train the MLP
+      if (scores) scores[kind] = 0.0;
+      continue;
+    }
+    kt_status st = kt_fit_selector(hh, dtype, (kt_selector)kind, fit_s.data(), fit_t.data(),
+                                   (int32_t)fit_s.size(), d, chosen, k, mlp, ws, ws_bytes, stream);
+    if (st != KT_OK) return st;
+    for (int32_t e = 0; e < nv; ++e)
+      if ((st = model_select(h, dtype, &val_s[e], &picks[e])) != KT_OK) return st;
+    double log_sum = 0.0;
+    for (int32_t e = 0; e < nv; ++e) {
+      const int64_t* t = &val_t[(size_t)e * d];
+      int64_t tb = 0;
+      for (int32_t j = 0; j < d; ++j)
+        if (t[j] > 0 && (tb == 0 || t[j] < tb)) tb = t[j];
+      const int64_t tu = t[picks[e]];
+      if (tb <= 0 || tu <= 0) return fail(h, KT_EINVAL, "validation row without a measured time");
+      log_sum += log((double)tb / (double)tu);
+    }
+    const double score = exp(log_sum / nv);
+    if (scores) scores[kind] = score;
+    if (score > best) { best = score; best_kind = kind; }
+  }
+  *kind_out = best_kind;
+  return kt_fit_selector(hh, dtype, (kt_selector)best_kind, shapes, time_ns, n, d, chosen, k, mlp,
+                         ws, ws_bytes, stream);
 }
 
 }  // extern "C"

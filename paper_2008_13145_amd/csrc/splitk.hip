@@ -154,7 +154,10 @@ kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits,
   }
   const int64_t plane = s->batch * s->M * s->N;
   if (!workspace || ws_bytes < (size_t)S * plane * 4)
-    return fail(h, KT_EWORKSPACE, "split-K workspace smaller than splits * batch * M * N floats");
+    return fail(h, KT_EWORKSPACE, "split-K with " + std::to_string(S) + " slices needs " +
+                                      std::to_string((size_t)S * plane * 4) +
+                                      " bytes of partial planes (slices * batch * M * N floats), got " +
+                                      std::to_string(workspace ? ws_bytes : 0));
   int32_t cfg = config_id;
   if (cfg < 0) {   // the selector sees the partial products as one batched GEMM
     kt_shape ps = *s;

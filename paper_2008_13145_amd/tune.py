@@ -42,46 +42,19 @@ DEPLOY_LIB = os.path.join(HERE, "libkt_deploy.so")
 
 
 NORM_NAMES = ("relative", "raw_cutoff", "std_cutoff", "sigmoid")
+REP_NAMES = {0: "mean", 1: "geomean", 2: "centroid"}
 
 
 def select_pruning(h, T_train, k, seed, n_init=10, max_iter=300, workspace=None, ws_bytes=0,
                    stream=None):
-    """k-means pruning (section 4.1) under each normalization of section 3.4,
-    keeping the one whose chosen set scores best on the training rows by the
-    paper's own measure: the geometric mean over rows of t_best / (fastest
-    chosen kernel's time).  Ties keep the earlier normalization.  Returns
-    {"norm": index, "norm_name", "chosen", "inertia", "train_ceiling": {name:
-    score}}."""
-    T_train = np.asarray(T_train, dtype=np.int64)
-    t_best = T_train.min(axis=1).astype(np.float64)
-    best = None
-    scores = {}
-    for norm, name in enumerate(NORM_NAMES):
-        res = h.prune(T_train, k, norm=norm, seed=seed, n_init=n_init, max_iter=max_iter,
-                      workspace=workspace, ws_bytes=ws_bytes, stream=stream)
-        chosen = [int(c) for c in res["chosen"]]
-        score = float(np.exp(np.mean(np.log(t_best / T_train[:, chosen].min(axis=1)))))
-        scores[name] = round(score, 6)
-        if best is None or score > best[0]:
-            best = (score, norm, chosen, int(res["inertia"]))
-    return {"norm": best[1], "norm_name": NORM_NAMES[best[1]], "chosen": best[2],
-            "inertia": best[3], "train_ceiling": scores}
-
-
-def clusters_to_configs(Xq, labels, k):
-    """Representative configuration per cluster (section 4.2) from its
-    members' rounded mean normalized row: the configuration with the largest
-    mean value not already taken (lowest index on ties), in cluster order."""
-    Xq = np.asarray(Xq, dtype=np.int64)
-    labels = np.asarray(labels)
-    chosen = []
-    for j in range(k):
-        rows = Xq[labels == j]
-        nj = len(rows)
-        m = (2 * rows.sum(axis=0) + nj) // (2 * nj) if nj else np.zeros(Xq.shape[1], np.int64)
-        order = sorted(range(Xq.shape[1]), key=lambda f: (-int(m[f]), f))
-        chosen.append(next(f for f in order if f not in chosen))
-    return chosen
+    """k-means pruning (section 4.1) under the normalization of section 3.4
+    whose chosen set keeps the most of the optimum on the training rows
+    (kt_prune_auto).  Returns {"norm", "norm_name", "chosen",
+    "train_ceiling": {name: score}}."""
+    r = h.prune_auto(T_train, k, seed=seed, n_init=n_init, max_iter=max_iter,
+                     workspace=workspace, ws_bytes=ws_bytes, stream=stream)
+    return {"norm": r["norm"], "norm_name": NORM_NAMES[r["norm"]], "chosen": r["chosen"],
+            "train_ceiling": {name: round(v, 6) for name, v in zip(NORM_NAMES, r["scores"])}}
 
 
 def normalized_table(h, T, norm, stream=None):
@@ -97,33 +70,39 @@ def normalized_table(h, T, norm, stream=None):
     return out.cpu().numpy().view(np.uint16)
 
 
-def tree_pruning(h, T_train, shapes, k, norm, stream=None):
-    """Decision-tree pruning (section 4.1): GPU normalization, then the
-    library's regression tree over the problem shapes."""
-    return h.prune_tree(shapes, normalized_table(h, T_train, norm, stream), k)
+def tree_pruning(h, T_train, shapes, k, norm, rep=0, stream=None):
+    """Decision-tree pruning (section 4.1) on the GPU-normalized table: the
+    leaves' rounded means pick the kernels (rep 0, kt_prune_tree) or their
+    members' geometric means (rep 1, section 4.2's rule for label-only
+    clusters)."""
+    Xq = normalized_table(h, T_train, norm, stream)
+    if rep == 0:
+        return h.prune_tree(shapes, Xq, k)
+    labels, n_leaves = h.prune_tree_leaves(shapes, Xq, k)
+    return h.representatives(Xq, labels, n_leaves, k, rep)
 
 
-def pca_pruning(h, T_train, k, seed, dims, norm, n_init=10, max_iter=300, workspace=None,
+def kmeans_pruning(h, T_train, k, seed, norm, rep=0, n_init=10, max_iter=300, workspace=None,
+                   ws_bytes=0, stream=None):
+    """k-means pruning (section 4.1): each centroid's best configuration
+    (rep 0, kt_prune) or the best for its members' geometric mean (rep 1)."""
+    r = h.prune(T_train, k, norm=norm, seed=seed, n_init=n_init, max_iter=max_iter,
+                workspace=workspace, ws_bytes=ws_bytes, stream=stream)
+    if rep == 0:
+        return r["chosen"]
+    return h.representatives(normalized_table(h, T_train, norm, stream), r["labels"], k, k, rep)
+
+
+def pca_pruning(h, T_train, k, seed, dims, norm, rep=2, n_init=10, max_iter=300, workspace=None,
                 ws_bytes=0, stream=None):
-    """k-means pruning in a reduced space (section 4.1: principal components
-    of the normalized table before clustering).  The table is normalized on
-    the GPU; the leading `dims` principal components of its rows (FP64 SVD
-    on the host) are quantized to 16 bits with one scale for all coordinates
-    (so Euclidean geometry is kept), clustered with the library's integer
-    k-means, and each cluster mapped back to a configuration by
-    clusters_to_configs.  Returns {"chosen", "inertia", "explained"}."""
-    Xq = normalized_table(h, T_train, norm, stream).astype(np.int64)
-    Xf = Xq / 65535.0
-    Xc = Xf - Xf.mean(axis=0)
-    _, S, Vt = np.linalg.svd(Xc, full_matrices=False)
-    Z = Xc @ Vt[:dims].T
-    lo, span = float(Z.min()), float(Z.max() - Z.min())
-    U = np.zeros(Z.shape, np.uint16) if span == 0 else np.rint((Z - lo) / span * 65535).astype(np.uint16)
-    km = h.kmeans_u16(U, k, seed, n_init, max_iter, workspace=workspace, ws_bytes=ws_bytes,
-                      stream=stream)
-    var = S ** 2
-    return {"chosen": clusters_to_configs(Xq, km["labels"], k), "inertia": km["inertia"],
-            "explained": float(var[:dims].sum() / var.sum()) if var.sum() > 0 else 1.0}
+    """PCA + k-means pruning (section 4.1, kt_prune_pca): the leading `dims`
+    principal components of the normalized training rows, the library's
+    integer k-means on their 16-bit quantization, and each cluster's kernel
+    from its centroid read back in the original coordinates (rep 2) or from
+    its members' geometric mean (rep 1).  Returns {"chosen", "inertia",
+    "explained", "labels"}."""
+    return h.prune_pca(T_train, k, norm, dims, rep=rep, seed=seed, n_init=n_init,
+                       max_iter=max_iter, workspace=workspace, ws_bytes=ws_bytes, stream=stream)
 
 
 def load_table(path):

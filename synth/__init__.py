@@ -150,6 +150,20 @@ def train_test_split(n_shapes: int = 300, n_train: int = 240, seed: int = SEED +
     return sorted(int(i) for i in perm[:n_train]), sorted(int(i) for i in perm[n_train:])
 
 
+def train_validation_split(train_shapes, n_val: int = 48, seed: int = SEED + 21):
+    """Seeded split of the training shapes into (fitting shapes, validation
+    shapes), each sorted: the validation shapes choose between selectors
+    without touching the test shapes."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(len(train_shapes))
+    ids = [int(train_shapes[i]) for i in perm]
+    return sorted(ids[n_val:]), sorted(ids[:n_val])
+
+
+def shape_of_row(row: int, n_layouts: int = 4) -> int:
+    return row // n_layouts
+
+
 def rows_of_shapes(shape_ids, n_layouts: int = 4):
     return [s * n_layouts + l for s in shape_ids for l in range(n_layouts)]
 

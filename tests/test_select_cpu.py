@@ -65,8 +65,9 @@ def test_save_load_roundtrip_and_corruption(kt, tmp_path):
     for s in shapes[::5]:
         assert h2.select(*s) == h.select(*s)
     txt = open(p).read()
-    for bad in (txt.replace("KTSEL 2", "KTSEL 9"), txt[: len(txt) // 2], txt.replace("tree", "tre"),
-                txt.replace("chosen 3 1 2 5", "chosen 3 1 2 999"), txt.replace("dtype 0", "dtype 7")):
+    for bad in (txt.replace("KTSEL 3", "KTSEL 9"), txt[: len(txt) // 2], txt.replace("tree", "tre"),
+                txt.replace("chosen 3 1 2 5", "chosen 3 1 2 999"), txt.replace("dtype 0", "dtype 7"),
+                txt.replace("box 1 1", "box 2 1"), txt.replace("box 1 1", "box 1")):
         q = str(tmp_path / "bad.txt")
         open(q, "w").write(bad)
         h3 = kt.Handle(-1)
@@ -76,6 +77,34 @@ def test_save_load_roundtrip_and_corruption(kt, tmp_path):
     with pytest.raises(kt.KtError) as e:
         kt.Handle(-1).load(str(tmp_path / "missing.txt"))
     assert e.value.status == -6
+
+
+def test_training_box_saved_and_version_2_files(kt, tmp_path):
+    rng = np.random.default_rng(7)
+    shapes, T = _table(rng, 40, 12, 5)
+    h = kt.Handle(-1)
+    h.fit_selector(1, shapes, T, [0, 4, 7])
+    info = h.selector_info()
+    S = np.array(shapes)
+    assert info["kind"] == 1 and info["chosen"] == [0, 4, 7] and info["fallback"] == 1
+    assert info["box_lo"] == S[:, :4].min(axis=0).tolist()
+    assert info["box_hi"] == S[:, :4].max(axis=0).tolist()
+    h.set_fallback(0)
+    h.fit_selector(2, shapes, T, [0, 4, 7])        # the setting survives a refit
+    assert h.selector_info()["fallback"] == 0
+    p = str(tmp_path / "sel.txt")
+    h.save(p)
+    h2 = kt.Handle(-1)
+    h2.load(p)
+    assert h2.selector_info() == h.selector_info()
+    # a version 2 file (no box line) loads without a training box
+    old = "".join(l for l in open(p) if not l.startswith("box")).replace("KTSEL 3", "KTSEL 2")
+    q = str(tmp_path / "v2.txt")
+    open(q, "w").write(old)
+    h3 = kt.Handle(-1)
+    h3.load(q)
+    assert h3.selector_info()["box_hi"] == [-1] * 4
+    assert all(h3.select(*s) == h.select(*s) for s in shapes[::3])
 
 
 def test_select_before_fit(kt):

@@ -336,32 +336,6 @@ def test_kmeans_u16_bitwise(gpu, kind, n, d, k):
     assert np.array_equal(got["centroids"], ref["centroids"])
 
 
-def test_pca_pruning_matches_oracle_steps(gpu):
-    """Pruning in a reduced space: the library's pipeline (GPU normalization,
-    host PCA and 16-bit quantization, GPU k-means, member-mean -> config)
-    gives the configurations the oracle's normalization, k-means and
-    centroid rule give on the same principal-component scores."""
-    kt_mod = __import__("paper_2008_13145_amd")
-    from paper_2008_13145_amd import tune
-    h, torch = gpu
-    rng = np.random.default_rng(21)
-    T = _planted_table(rng, 960, 164, 9)
-    k, dims, norm, seed = 8, 16, 2, 13145
-    ws_bytes = kt_mod.Handle.prune_workspace_bytes(960, dims, k, 10)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    got = tune.pca_pruning(h, T, k, seed, dims, norm, workspace=ws, ws_bytes=ws_bytes)
-    Xq = onz.normalize(T, norm).astype(np.int64)
-    Xf = Xq / 65535.0
-    Xc = Xf - Xf.mean(axis=0)
-    Z = Xc @ np.linalg.svd(Xc, full_matrices=False)[2][:dims].T
-    U = np.rint((Z - Z.min()) / (Z.max() - Z.min()) * 65535).astype(np.int64)
-    ref = okm.kmeans(U, k, _draws(seed, 10, k), 300)
-    C = okm.update(Xq, ref["labels"], np.zeros(len(Xq), np.int64), np.zeros((k, 164), np.int64))
-    assert got["inertia"] == ref["inertia"]
-    assert got["chosen"] == okm.centroids_to_configs(C)
-    assert 0 < got["explained"] <= 1
-
-
 @pytest.mark.parametrize("norm", [0, 2])
 def test_tree_pruning_on_gpu_normalized_table(gpu, norm):
     """Decision-tree pruning fed by the GPU normalization equals the oracle's
