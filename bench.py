@@ -716,6 +716,29 @@ def conv_section(kt, h, tune, problems_conv_path, sel_kinds, fit_args):
     return out
 
 
+def calibrate_counters(log2n=28, reps=3):
+    """A kernel of known HBM traffic for scaling rocprofv3's FETCH_SIZE and
+    WRITE_SIZE: the library's BF16 conversion reads 4 bytes and writes 2
+    bytes per element, each once, on a buffer far larger than the caches.
+    Run under `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) and divide the
+    printed bytes per dispatch by the counter's reading."""
+    import torch
+
+    import paper_2008_13145_amd as kt
+    n = 1 << log2n
+    h = kt.Handle(0)
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    h.fill_uniform(x, n, 1)
+    y = torch.empty(n, dtype=torch.int16, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        h.convert_bf16(x, n, y)
+    torch.cuda.synchronize()
+    h.close()
+    print(json.dumps({"kernel": "cvt_bf16_kernel", "elements": n, "fetch_bytes": 4 * n,
+                      "write_bytes": 2 * n, "dispatches": reps}), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -728,7 +751,12 @@ def main(argv=None):
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16/FP8 sections")
+    ap.add_argument("--calibrate-counters", action="store_true",
+                    help="only run the known-traffic conversion kernel (HBM counter scaling)")
     a = ap.parse_args(argv)
+    if a.calibrate_counters:
+        calibrate_counters()
+        return 0
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
               "design is described in DESIGN.md and not built", file=sys.stderr)

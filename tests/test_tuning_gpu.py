@@ -144,7 +144,11 @@ def test_select_batch_matches_host_walk(gpu):
         d_ids = torch.zeros(len(queries), dtype=torch.int32, device="cuda")
         h.select_batch(d_shapes, len(queries), d_ids)
         torch.cuda.synchronize()
+        # the device walk is the model's pick; compare with the host walk
+        # without the out-of-range fallback (the two extra queries lie outside)
+        h.set_fallback(0)
         want = [h.select(*q) for q in queries]
+        h.set_fallback(1)
         assert d_ids.cpu().tolist() == want
         ref = cart.fit(np.array(problems), cart.labels_from_times(T, chosen), 5,
                        *cart.TREE_PARAMS["ABC"[kind]])
