@@ -166,6 +166,31 @@ kt_status kt_gemm_splitk(kt_handle h, kt_dtype in_dtype, const kt_shape* s, int3
  * every automatic choice, min(64 * batch * M * N, 2^28) floats.  Host only. */
 kt_status kt_gemm_splitk_workspace_bytes(const kt_shape* s, int32_t splits, size_t* bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): kt_gemm_splitk
+ * with the partial planes in a static device array the library owns instead
+ * of a caller workspace.  Same arguments, kernels, results (bit for bit) and
+ * slice choice as kt_gemm_splitk.  The array holds
+ * kt_gemm_splitk_noalloc_max_bytes() bytes (32 MiB) on every GPU the
+ * library runs on, from kt_create on that device until the process ends; a
+ * product that needs more (slices * batch * M * N * 4 bytes) returns
+ * KT_EWORKSPACE before anything is launched.  Nothing is allocated: no
+ * hipMalloc, hipFree or allocating library call, so config_id = -1 with an
+ * exhaustive selector works only for shapes it has already timed
+ * (KT_EUNSUPPORTED otherwise).  Nothing in the array needs clearing: every
+ * partial plane is fully written before the reduction reads it.  All calls
+ * on one GPU share the one array and keep the last call's contents, so
+ * calls that overlap on one GPU (other streams, other threads, other
+ * handles) race; serialize them, e.g. on one stream. */
+kt_status kt_gemm_splitk_noalloc(kt_handle h, kt_dtype in_dtype, const kt_shape* s,
+                                 int32_t splits, float alpha, const void* A, int64_t lda,
+                                 int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+                                 float beta, float* C, int64_t ldc, int64_t strideC,
+                                 const float* scaleA, const float* scaleB, int32_t config_id,
+                                 void* stream, int32_t* used_splits);
+/* Size of the static scratch of kt_gemm_splitk_noalloc in bytes.  Host only. */
+kt_status kt_gemm_splitk_noalloc_max_bytes(size_t* bytes);
+
 /* ------------------------------------------------------------ convolution */
 
 /* Convolution layers through the selected GEMMs (section 6 runs VGG16, whose
@@ -498,7 +523,7 @@ kt_status kt_fit_selector_validated(kt_handle h, kt_dtype dtype, const kt_shape*
  * whose M, N, K or batch lies outside the range the selector was fitted on
  * is not given to the model; the chosen configurations are timed on it once
  * (scratch as above, synchronizing) and the fastest is cached for the
- * shape. */
+ * shape.  Entry points that must not allocate keep the model's pick. */
 kt_status kt_select(kt_handle h, kt_dtype dtype, const kt_shape* s, int32_t* config_id);
 
 /* Turn the out-of-range fallback of kt_select on (1) or off (0) for the

@@ -94,6 +94,10 @@ _SIGS = {
                                c_i64, c_vp, c_i64, c_i64, c_f32, c_vp, c_i64, c_i64, c_vp, c_vp,
                                c_i32, c_vp, c_sz, c_vp, ctypes.POINTER(c_i32)]),
     "kt_gemm_splitk_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
+    "kt_gemm_splitk_noalloc": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_f32, c_vp,
+                                       c_i64, c_i64, c_vp, c_i64, c_i64, c_f32, c_vp, c_i64, c_i64,
+                                       c_vp, c_vp, c_i32, c_vp, ctypes.POINTER(c_i32)]),
+    "kt_gemm_splitk_noalloc_max_bytes": (c_i32, [ctypes.POINTER(c_sz)]),
     "kt_conv2d_gemm_shape": (c_i32, [ctypes.POINTER(ConvShape), c_i32, ctypes.POINTER(Shape)]),
     "kt_conv2d_workspace_bytes": (c_i32, [ctypes.POINTER(ConvShape), c_i32, c_i32,
                                           ctypes.POINTER(c_sz)]),
@@ -335,6 +339,29 @@ class Handle:
                                           int(sC), _ptr(scaleA), _ptr(scaleB), int(config_id),
                                           _ptr(workspace), int(ws_bytes), _stream(stream),
                                           ctypes.byref(used)))
+        return used.value
+
+    @staticmethod
+    def splitk_noalloc_max_bytes() -> int:
+        b = c_sz()
+        st = lib().kt_gemm_splitk_noalloc_max_bytes(ctypes.byref(b))
+        if st != 0:
+            raise KtError(st, "split-K scratch size query")
+        return b.value
+
+    def gemm_splitk_noalloc(self, A, B, C, splits, transA=0, transB=0, alpha=1.0, beta=0.0,
+                            config_id=-1, dtype=F32, scaleA=None, scaleB=None, stream=None):
+        """kt_gemm_splitk_noalloc on tensors laid out as for gemm() (partial
+        planes in the library's static device scratch); returns the number of
+        K slices used."""
+        shp, lda, sA, ldb, sB, ldc, sC = self._operands(A, B, C, transA, transB)
+        used = c_i32(0)
+        self._check(self.L.kt_gemm_splitk_noalloc(self.h, dtype, ctypes.byref(shp), int(splits),
+                                                  float(alpha), _ptr(A), int(lda), int(sA),
+                                                  _ptr(B), int(ldb), int(sB), float(beta), _ptr(C),
+                                                  int(ldc), int(sC), _ptr(scaleA), _ptr(scaleB),
+                                                  int(config_id), _stream(stream),
+                                                  ctypes.byref(used)))
         return used.value
 
     # -------------------------------------------------------- convolution

@@ -163,6 +163,14 @@ kt_status kt_create(kt_handle* out, int device) {
   }
   h->device = device;
   build_tables(h);
+  if (device >= 0) {
+    kt_status st = noalloc_scratch_init(h);
+    if (st != KT_OK) {
+      g_create_err = h->err;
+      delete h;
+      return st;
+    }
+  }
   *out = reinterpret_cast<kt_handle>(h);
   return KT_OK;
 }

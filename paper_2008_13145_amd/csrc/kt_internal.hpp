@@ -67,6 +67,8 @@ struct Ctx {
   void* d_lut = nullptr;           // device sigmoid table (handle-owned)
   kt_grouped_opts grouped_best{};  // autotuner result for grouped GEMM
   bool grouped_tuned = false;
+  void* noalloc_scratch = nullptr; // device address of the static split-K scratch
+  bool forbid_alloc = false;       // set while an entry point that must not allocate runs
 };
 
 // Record an error message on the handle and return the status.
@@ -104,6 +106,10 @@ void free_selector_device(Ctx* h, int dtype);
 // host memory; synchronizes the stream.
 kt_status normalize_table_host(Ctx* h, const int64_t* time_ns, int32_t n, int32_t d, kt_norm norm,
                                void* workspace, size_t ws_bytes, hipStream_t st, uint16_t* out);
+
+// Looks up the device address of the static split-K scratch for the handle's
+// device (once per device, that device current) and keeps it on the handle.
+kt_status noalloc_scratch_init(Ctx* h);
 
 // Sigmoid lookup table of the normalization (Q16 -> Q16).
 const std::vector<uint16_t>& sigmoid_table(Ctx* h);

@@ -200,6 +200,10 @@ static int64_t elem_bytes_sel(int dtype) { return dtype == KT_F32 ? 4 : dtype ==
 static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
                                  const std::vector<int32_t>& cands, int32_t* out) {
   if (!need_device(h)) return KT_EINVAL;
+  if (h->forbid_alloc)
+    return fail(h, KT_EUNSUPPORTED, "the exhaustive selector would allocate scratch operands for "
+                                    "an unseen shape; this entry point allocates nothing (select "
+                                    "the shape once with kt_select first, or pass a config id)");
   const int64_t eb = elem_bytes_sel(dtype);
   const int64_t a_rows = s->transA ? s->K : s->M, a_cols = s->transA ? s->M : s->K;
   const int64_t b_rows = s->transB ? s->N : s->K, b_cols = s->transB ? s->K : s->N;
@@ -340,9 +344,10 @@ static kt_status model_select(Ctx* h, int dtype, const kt_shape* s, int32_t* id)
 kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
   const SelState& S = h->sel[dtype];
   // Outside the training box the model is extrapolating: time the chosen
-  // configurations once instead.
+  // configurations once instead (not from an entry point that must not
+  // allocate, where the model's pick stands).
   if (S.kind >= KT_SEL_DT_A && S.kind <= KT_SEL_MLP && S.fallback && S.have_box &&
-      outside_box(S, *s) && h->device >= 0)
+      outside_box(S, *s) && !h->forbid_alloc && h->device >= 0)
     return fallback_select(h, dtype, s, id);
   return model_select(h, dtype, s, id);
 }

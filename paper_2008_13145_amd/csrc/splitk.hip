@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 
 #include "kt_internal.hpp"
@@ -212,3 +213,73 @@ kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits,
 }
 
 }  // namespace kt
+
+// ---------------------------------------------------------------------------
+// Split-K without allocation: the partial planes live in a static device
+// array of NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// so its device address is looked up once per device (with that device
+// current) and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+
+namespace kt {
+
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
+constexpr int MAX_DEVICES = 64;
+
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+}  // namespace
+
+kt_status noalloc_scratch_init(Ctx* h) {
+  if (h->device < 0) return KT_OK;
+  if (h->device >= MAX_DEVICES) return fail(h, KT_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[h->device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(split-K scratch)");
+    if (!p) return fail(h, KT_EHIP, "hipGetSymbolAddress returned NULL for the split-K scratch");
+    g_scratch_addr[h->device] = p;
+  }
+  h->noalloc_scratch = g_scratch_addr[h->device];
+  return KT_OK;
+}
+
+}  // namespace kt
+
+extern "C" {
+
+kt_status kt_gemm_splitk_noalloc_max_bytes(size_t* bytes) {
+  if (!bytes) return fail(nullptr, KT_EINVAL, "NULL argument");
+  *bytes = NOALLOC_SCRATCH_BYTES;
+  return KT_OK;
+}
+
+kt_status kt_gemm_splitk_noalloc(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_t splits,
+                                 float alpha, const void* A, int64_t lda, int64_t strideA,
+                                 const void* B, int64_t ldb, int64_t strideB, float beta, float* C,
+                                 int64_t ldc, int64_t strideC, const float* scaleA,
+                                 const float* scaleB, int32_t config_id, void* stream,
+                                 int32_t* used_splits) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!need_device(h)) return KT_EINVAL;
+  if (!h->noalloc_scratch) return fail(h, KT_EHIP, "split-K scratch address was not set up");
+  h->forbid_alloc = true;
+  kt_status st = splitk_gemm(h, dtype, s, splits, alpha, A, lda, strideA, B, ldb, strideB, beta,
+                             C, ldc, strideC, scaleA, scaleB, config_id, h->noalloc_scratch,
+                             NOALLOC_SCRATCH_BYTES, stream, used_splits, nullptr, 0, nullptr);
+  h->forbid_alloc = false;
+  if (st == KT_EWORKSPACE)
+    h->err = "kt_gemm_splitk_noalloc: the static split-K scratch holds " +
+             std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes; " + h->err;
+  return st;
+}
+
+}  // extern "C"
