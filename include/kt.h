@@ -537,7 +537,9 @@ kt_status kt_set_fallback(kt_handle h, kt_dtype dtype, int32_t enabled);
 kt_status kt_selector_info(kt_handle h, kt_dtype dtype, int32_t* kind, int32_t* k,
                            int32_t* chosen, int64_t* box, int32_t* fallback);
 
-/* Same for n shapes on the device: d_shapes and d_ids are device arrays. */
+/* Same for n shapes on the device: d_shapes and d_ids are device arrays.
+ * Always the fitted model's pick (the out-of-range fallback of kt_select
+ * times kernels on the host side and does not apply here). */
 kt_status kt_select_batch(kt_handle h, kt_dtype dtype, const kt_shape* d_shapes, int32_t n,
                           int32_t* d_ids, void* stream);
 
