@@ -826,7 +826,8 @@ def main(argv=None):
     # pick on the held-out rows (the out-of-range fallback off)
     tr_shapes = [problems[r] for r in tr_rows]
     fit_ms = {}
-    mws_bytes = kt.Handle.mlp_workspace_bytes(len(tr_rows), n_cfg, k)
+    # sized for the largest k of the comparison over k below
+    mws_bytes = kt.Handle.mlp_workspace_bytes(len(tr_rows), n_cfg, max(k, 15))
     mws = torch.empty(mws_bytes, dtype=torch.uint8, device="cuda")
     h.set_fallback(0)
     for kind in (0, 1, 2, 3):
