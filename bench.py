@@ -180,7 +180,7 @@ def splitk_section(kt, h, torch, T, problems, plans, chosen, stream, reps=5):
     exhaustive-best plain launch against the best split-K launch over splits
     {2, 4, 8, 16} x (that configuration and the k deployed ones), both timed
     live on resident operands (mean of `reps` launches after one warm-up)."""
-    cfgs = h.configs()
+    cfgs = h.kernels()
     rows = []
     for r, (M, N, K, bt, ta, tb) in enumerate(problems):
         bm, bn = cfgs[int(np.argmin(T[r]))][:2]
@@ -604,7 +604,8 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
         if not os.path.exists(path):
             continue
         TL, PL, CL, metaL = tune.load_table(path)
-        if not (TL >= 0).all() or [tuple(int(v) for v in p) for p in PL] != problems:
+        if not (TL >= 0).all() or [tuple(int(v) for v in p) for p in PL] != problems or \
+                [tuple(c) for c in CL.tolist()] != h.kernels(dt)[:len(CL)]:
             continue
         tl = TL.min(axis=1).astype(np.float64)
         ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), TL.shape[1], k, 10)
@@ -658,12 +659,14 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
                              for s_ in range(steps)]).mean(axis=0)
         inst = {}
         for i, p in enumerate(problems):
+            if h.get_kernel(picks[i], dt)[0][4] > 1:     # split-K picks run several kernels
+                continue
             key = (picks[i], p[4], p[5])
             inst[key] = inst.get(key, 0.0) + t_launch[i]
         dom = max(inst, key=inst.get)
         dom_rows = [i for i, p in enumerate(problems) if (picks[i], p[4], p[5]) == dom]
         dom_tf = float(flops[dom_rows].sum()) / (float(t_launch[dom_rows].sum()) * 1e-3) / 1e12
-        bm, bn, tt, bk = h.get_config(dom[0], dt)
+        bm, bn, tt, bk = h.get_kernel(dom[0], dt)[0][:4]
         out[name] = {
             "live_tflops": round(float(flops.sum()) / (ms * 1e-3) / 1e12, 2),
             "ms_per_step": round(ms, 3),
@@ -676,7 +679,7 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
             "selector_pct_of_optimal_test": per_kind,
             "selector_validation_scores": {SEL_NAMES[i]: round(100 * v, 2) for i, v in enumerate(vscores)},
             "kmeans_ceiling_test": round(100 * ceil["geomean"], 2),
-            "chosen": [list(h.get_config(c, dt)) for c in chosen],
+            "chosen": [list(h.get_kernel(c, dt)[0]) for c in chosen],
             "normalization": sel["norm_name"], "train_ceiling_by_normalization": sel["train_ceiling"],
             "accuracy_bound_rel_frobenius": 1e-2 if dt == kt.BF16 else 4e-2,
             "roofline": {"bound": "mfma", "kernel": f"gemm_lp_kernel<{eb}, {bm}, {bn}, {tt}, {bk}, "
@@ -696,8 +699,8 @@ def conv_section(kt, h, tune, problems_conv_path, sel_kinds, fit_args):
     if not os.path.exists(problems_conv_path):
         return None
     TC, PC, CC, metaC = tune.load_table(problems_conv_path)
-    if not (TC >= 0).all():
-        return None
+    if not (TC >= 0).all() or TC.shape[1] != fit_args[1].shape[1]:
+        return None   # incomplete, or measured over other kernels than the sweep table
     probs = [tuple(int(v) for v in p) for p in PC]
     F = np.array([2.0 * p[0] * p[1] * p[2] * p[3] for p in probs])
     tb = TC.min(axis=1).astype(np.float64)
@@ -782,7 +785,11 @@ def main(argv=None):
     te_rows = synth.rows_of_shapes(test)
 
     h = kt.Handle(0)
-    assert [tuple(c) for c in C.tolist()] == h.configs()
+    kernels = h.kernels()
+    assert [tuple(c) for c in C.tolist()] == kernels[:n_cfg], "table columns are not this build's kernels"
+    # partial planes for the split-K kernels kt_gemm runs (selected or forced)
+    gemm_ws = torch.empty(kt.SPLIT_PLANE_CAP, dtype=torch.uint8, device="cuda")
+    h.set_workspace(gemm_ws)
     _log(f"bench: table {table_path} ({n_prob} problems x {n_cfg} configs)")
     stream = torch.cuda.current_stream()
 
@@ -985,9 +992,11 @@ def main(argv=None):
     value = total_flops / (ms_per_step * 1e-3) / 1e12
 
     # dominant kernel: the (configuration, layout) instantiation with the most time
-    cfgs = h.configs()
+    cfgs = kernels
     inst_time = {}
     for i, p in enumerate(problems):
+        if cfgs[picks_all[i]][4] > 1:     # split-K picks run several kernels
+            continue
         key = (picks_all[i], p[4], p[5])
         inst_time[key] = inst_time.get(key, 0.0) + t_launch[i]
     dom = max(inst_time, key=inst_time.get)
@@ -998,10 +1007,11 @@ def main(argv=None):
                                                   problems[i][0] * problems[i][1]) for i in dom_rows))
     dom_ms = float(t_launch[dom_rows].sum())
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
-    bm, bn, tt, bk = cfgs[dom[0]]
+    bm, bn, tt, bk = cfgs[dom[0]][:4]
     dom_name = f"gemm_f32_kernel<{bm}, {bn}, {tt}, {bk}, {dom[1]}, {dom[2]}>"
 
     # exhaustive-best comparison: live launch times vs the table's best
+    t_best = T.min(axis=1).astype(np.float64)
     pct_exh_live = float(t_best.sum() * 1e-6 / t_launch.sum())
     out = {
         "metric": "GEMM TFLOP/s; % of exhaustive-best config; % MFMA peak; selector regret",

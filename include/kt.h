@@ -114,9 +114,46 @@ int32_t kt_abi_version(void);
 kt_status kt_num_configs(kt_handle h, kt_dtype dtype, int32_t* n);
 /* Configuration `id` (0 <= id < n) of a dtype.  KT_EINVAL if out of range. */
 kt_status kt_get_config(kt_handle h, kt_dtype dtype, int32_t id, kt_config* out);
-/* 1 if configuration `id` is compiled for the (transA, transB) layout. */
+/* 1 if kernel `id` (a configuration, or a split-K variant through its base
+ * configuration) is compiled for the (transA, transB) layout. */
 kt_status kt_config_compiled(kt_handle h, kt_dtype dtype, int32_t id, int32_t transA,
                              int32_t transB, int32_t* compiled);
+
+/* ----------------------------------------------------------------- kernels */
+
+/* The kernels of a dtype, the columns of its sweep table and the ids that
+ * pruning and selection return: its configurations (kernel id = configuration
+ * id, 0 <= id < kt_num_configs) followed by split-K variants, the separate
+ * kernel type section 3 names for deep products with few output tiles (K
+ * divided among work-groups, partial results reduced afterwards).  A variant
+ * runs a base configuration over `slices` slices of K exactly as
+ * kt_gemm_splitk(splits = slices, config_id = base) does, when its partial
+ * planes (S * batch * M * N floats with S the slices really used, at most
+ * 256 MiB) fit the workspace it is given; otherwise it runs as the base
+ * configuration unsplit.  Variants: for each square work-group tile edge 16,
+ * 32, 64 and 128, the configuration with the deepest K tile and then the most
+ * waves, over 2, 4, 8 and 16 slices (16 variants per dtype).  A variant
+ * needs no code of its own: it is compiled wherever its base is. */
+kt_status kt_num_kernels(kt_handle h, kt_dtype dtype, int32_t* n);
+/* Kernel `id`: its configuration (the base's for a variant), the base
+ * configuration id (id itself for a configuration) and the slice count
+ * (1 for a configuration).  All outputs host pointers.  KT_EINVAL if out of
+ * range. */
+kt_status kt_get_kernel(kt_handle h, kt_dtype dtype, int32_t id, kt_config* cfg,
+                        int32_t* base_id, int32_t* slices);
+/* Partial-plane bytes kernel `id` needs on shape s to run split (0 when it
+ * runs unsplit: a configuration, one slice, or planes beyond 256 MiB).
+ * Host only. */
+kt_status kt_kernel_workspace_bytes(kt_handle h, kt_dtype dtype, const kt_shape* s, int32_t id,
+                                    size_t* bytes);
+/* Device workspace (caller-owned, may be NULL with bytes 0) that kt_gemm
+ * gives a split-K kernel for its partial planes, whether selected or forced.
+ * The handle keeps the pointer, not the memory: it must stay allocated and
+ * untouched by the caller while kt_gemm work queued on any stream may use
+ * it, and kt_gemm calls of one handle that run split-K kernels on different
+ * streams at once race on it.  Without it (or when it is too small for a
+ * product) split-K kernels run as their base configuration unsplit. */
+kt_status kt_set_workspace(kt_handle h, void* workspace, size_t bytes);
 
 /* ------------------------------------------------------------------- GEMM */
 
@@ -125,7 +162,10 @@ kt_status kt_config_compiled(kt_handle h, kt_dtype dtype, int32_t id, int32_t tr
  * bit patterns, or FP8 e4m3 codes); C is always FP32.  FP8 multiplies the
  * product by alpha / (scaleA[0] * scaleB[0]) where scaleA/scaleB are device
  * pointers to the per-tensor quantization scales (NULL for other dtypes).
- * config_id >= 0 forces that configuration; -1 asks the fitted selector.
+ * config_id >= 0 forces that kernel (a configuration or a split-K variant,
+ * see kt_num_kernels; a variant takes its partial planes from the workspace
+ * set with kt_set_workspace); -1 asks the fitted selector, whose pick may be
+ * a split-K variant.
  * With beta == 0, C is never read (NaN in C does not propagate).  M, N or
  * batch == 0 is a no-op; K == 0 gives C = beta * C.  Unaligned pointers or
  * leading dimensions are never an error (FP32 rows load as dword-aligned
@@ -137,18 +177,30 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
                   const float* scaleA, const float* scaleB,
                   int32_t config_id, void* stream);
 
+/* Which pipeline the BF16 / FP8 kernels take for these operands (host only,
+ * nothing launched): *dma = 1 when every row of A and B starts on a 16-byte
+ * boundary (base, leading dimension and, for batch > 1, batch stride) and
+ * each operand's contiguous extent (K for an operand stored K-contiguous,
+ * M or N otherwise) is a whole number of 16-byte chunks -- tiles then move
+ * from HBM to LDS by LDS DMA with several stages in flight; otherwise 0
+ * (register-staged loads; same results).  Always 0 for KT_F32. */
+kt_status kt_lp_pipeline(kt_dtype dtype, const kt_shape* s, const void* A, int64_t lda,
+                         int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+                         int32_t* dma);
+
 /* Split-K form of kt_gemm for deep products with few output tiles, the
  * tall-skinny / very deep K case that section 3 names as its kernel's worst
  * (fix: divide the K range among work-groups).  The K range is cut into
  * S = ceil(K / kc) slices of depth kc = ceil(K / splits) rounded up to a
  * multiple of 64 (so S <= splits; the last slice may be shallower); slice q
- * is computed with configuration config_id (-1: the selector, asked for the
- * shape M, N, kc with batch * S items) into FP32 partial planes in the
+ * is computed with configuration config_id (-1: the configuration of the
+ * kernel the selector picks for the shape M, N, kc with batch * S items)
+ * into FP32 partial planes in the
  * workspace (device, dense, [S][batch][M][N]), and one reduction pass writes
  * C = alpha * (sum of the planes in slice order) + beta * C (C not read when
  * beta == 0).  Arguments and layouts as kt_gemm; 0 <= splits <= 64.
- * splits == 0 chooses S: the configuration is config_id, or the selector's
- * pick for the whole product, and S doubles from 1 while that configuration
+ * splits == 0 chooses S: the configuration is config_id, or the
+ * configuration of the selector's pick for the whole product, and S doubles from 1 while that configuration
  * fills fewer than 2048 work-groups (tiles x batch x S), each slice stays at
  * least 256 deep and S < 64.  When S == 1 (also splits == 1 or K <= 64)
  * this is exactly kt_gemm and needs no workspace.  *used_splits (host, may
@@ -232,7 +284,8 @@ kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, i
 /* y = conv(x, w) + bias, then ReLU when relu != 0.  x, w, bias (NULL = no
  * bias; Cout floats), y and workspace are device pointers; y must not alias
  * x or the workspace.  config_id: FP32 configuration of the GEMM, -1 = the
- * fitted selector on kt_conv2d_gemm_shape.  splits (im2col only; Winograd
+ * configuration of the kernel the fitted selector picks for
+ * kt_conv2d_gemm_shape (the layer's split is `splits`).  splits (im2col only; Winograd
  * takes 0 or 1 and never splits): 1 = the plain GEMM, otherwise the GEMM
  * runs as kt_gemm_splitk with this splits value (0 = automatic), which suits
  * the fully connected layers of a single image (M = 1, deep K).  Empty n, Ho
@@ -282,16 +335,21 @@ typedef struct {
   float alpha, beta;
 } kt_sweep_opts;
 
-/* Device workspace needed to sweep these shapes (operands of the largest
- * shape, 256-byte aligned). */
+/* Device workspace needed to sweep these shapes with any kernels: operands
+ * of the largest shape, 256-byte aligned, plus the largest partial planes
+ * any split-K variant of the dtype takes on it. */
 kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_dtype dtype,
                                    size_t* bytes);
-/* Time every (shape, configuration) pair (sections 3 and 3.1): for each shape
- * the operands are filled in the workspace, then each configuration is
- * launched `warmup` times and timed with HIP events over its reps; the mean
- * nanoseconds per launch go to time_ns[shape * n_configs + c] (host, int64).
- * config_ids (host) selects configurations (NULL = all of the dtype, in id
- * order).  Entries already >= 0 in time_ns are kept (resume).  The call
+/* Time every (shape, kernel) pair (sections 3 and 3.1): for each shape the
+ * operands are filled in the workspace, then each kernel is launched
+ * `warmup` times and timed with HIP events over its reps (a split-K variant
+ * as its slice launches plus reduction, its partial planes after the
+ * operands in the workspace); the mean nanoseconds per launch go to
+ * time_ns[shape * n_configs + c] (host, int64).  config_ids (host) selects
+ * kernels (NULL = all kernels of the dtype, configurations and split-K
+ * variants, in id order).  Entries already >= 0 in time_ns are kept
+ * (resume).  KT_EWORKSPACE if the workspace is smaller than a shape's
+ * operands plus the partial planes of the listed kernels.  The call
  * synchronizes `stream`. */
 kt_status kt_sweep(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n_shapes,
                    const int32_t* config_ids, int32_t n_configs, const kt_sweep_opts* opts,

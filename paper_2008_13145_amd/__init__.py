@@ -108,6 +108,14 @@ _SIGS = {
     "kt_fill_uniform": (c_i32, [c_vp, c_vp, c_i64, c_u64, c_i64, c_vp]),
     "kt_convert_bf16": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "kt_quantize_fp8": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "kt_num_kernels": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
+    "kt_get_kernel": (c_i32, [c_vp, c_i32, c_i32, ctypes.POINTER(Config), ctypes.POINTER(c_i32),
+                              ctypes.POINTER(c_i32)]),
+    "kt_kernel_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32,
+                                          ctypes.POINTER(c_sz)]),
+    "kt_set_workspace": (c_i32, [c_vp, c_vp, c_sz]),
+    "kt_lp_pipeline": (c_i32, [c_i32, ctypes.POINTER(Shape), c_vp, c_i64, c_i64, c_vp, c_i64, c_i64,
+                               ctypes.POINTER(c_i32)]),
     "kt_sweep_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_sweep": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_i32,
                          ctypes.POINTER(SweepOpts), c_vp, c_sz, c_vp, c_vp]),
@@ -163,6 +171,10 @@ _SIGS = {
                                         c_vp, c_sz, c_vp]),
     "kt_get_mlp": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_i32), c_vp]),
 }
+
+# Largest partial planes a split-K kernel takes from the kt_set_workspace
+# buffer; a workspace this large lets every split-K kernel run split.
+SPLIT_PLANE_CAP = 256 << 20
 
 _lib = None
 
@@ -263,6 +275,47 @@ class Handle:
 
     def configs(self, dtype=F32):
         return [self.get_config(i, dtype) for i in range(self.num_configs(dtype))]
+
+    def num_kernels(self, dtype=F32) -> int:
+        n = c_i32()
+        self._check(self.L.kt_num_kernels(self.h, dtype, ctypes.byref(n)))
+        return n.value
+
+    def get_kernel(self, id, dtype=F32):
+        """(bm, bn, t, bk, slices) of kernel `id` and its base configuration id."""
+        c, b, sl = Config(), c_i32(), c_i32()
+        self._check(self.L.kt_get_kernel(self.h, dtype, int(id), ctypes.byref(c), ctypes.byref(b),
+                                         ctypes.byref(sl)))
+        return (c.bm, c.bn, c.t, c.bk, sl.value), b.value
+
+    def kernels(self, dtype=F32):
+        """(bm, bn, t, bk, slices) per kernel id: configurations, then split-K variants."""
+        return [self.get_kernel(i, dtype)[0] for i in range(self.num_kernels(dtype))]
+
+    def kernel_workspace_bytes(self, M, N, K, batch=1, transA=0, transB=0, id=0, dtype=F32) -> int:
+        b = c_sz()
+        self._check(self.L.kt_kernel_workspace_bytes(self.h, dtype,
+                                                     ctypes.byref(shape(M, N, K, batch, transA, transB)),
+                                                     int(id), ctypes.byref(b)))
+        return b.value
+
+    @staticmethod
+    def lp_pipeline_dma(dtype, shp: Shape, A, lda, sA, B, ldb, sB) -> bool:
+        """True when BF16 / FP8 kernels run these operands through the LDS DMA pipeline."""
+        v = c_i32()
+        st = lib().kt_lp_pipeline(int(dtype), ctypes.byref(shp), _ptr(A), int(lda), int(sA), _ptr(B),
+                                  int(ldb), int(sB), ctypes.byref(v))
+        if st != 0:
+            raise KtError(st, "pipeline query")
+        return bool(v.value)
+
+    def set_workspace(self, ws, ws_bytes=None):
+        """Device buffer (tensor or pointer) kt_gemm gives split-K kernels; None clears it."""
+        if ws is None:
+            self._check(self.L.kt_set_workspace(self.h, None, 0))
+            return
+        n = ws_bytes if ws_bytes is not None else ws.numel() * ws.element_size()
+        self._check(self.L.kt_set_workspace(self.h, _ptr(ws), int(n)))
 
     def config_compiled(self, id, transA, transB, dtype=F32) -> bool:
         v = c_i32()
@@ -422,7 +475,7 @@ class Handle:
               target_ms=2.0, min_reps=3, max_reps=200, cut_factor=8.0, pause_ms=0.0, seed=13145,
               alpha=1.0, beta=0.0, dtype=F32, stream=None):
         arr = shapes_array(shapes)
-        n_cfg = self.num_configs(dtype) if config_ids is None else len(config_ids)
+        n_cfg = self.num_kernels(dtype) if config_ids is None else len(config_ids)
         if time_ns is None:
             time_ns = np.full((len(shapes), n_cfg), -1, dtype=np.int64)
         assert time_ns.dtype == np.int64 and time_ns.flags.c_contiguous

@@ -116,7 +116,9 @@ def build_deploy(jobs: int | None = None, verbose: bool = False):
     if not os.path.exists(spec_path):
         return None
     spec = json.load(open(spec_path))
-    return build(jobs=jobs, f32_ids=spec["chosen"], lp_ids=[],
+    # the configurations of the chosen kernels (a split-K variant runs its base's code)
+    ids = spec.get("config_ids", spec["chosen"])
+    return build(jobs=jobs, f32_ids=ids, lp_ids=[],
                  out=os.path.join(HERE, "libkt_deploy.so"), verbose=verbose, tag="deploy")
 
 

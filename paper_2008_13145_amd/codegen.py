@@ -12,6 +12,12 @@ instantiations over the four (transA, transB) layouts.
 
 A "deploy" build instantiates only chosen ids (section 4: only the pruned
 kernels ship in the library); ids keep their meaning, the rest are absent.
+
+Kernels: the configurations of a dtype (ids 0 .. n-1) are followed by its
+split-K variants (ids n, n+1, ...), the kernel type section 3 names for deep,
+under-filled products: a base configuration run over S slices of K plus a
+reduction.  A variant adds no code (it reuses its base's instantiation), so a
+deploy build that keeps the base keeps its variants.
 """
 from __future__ import annotations
 
@@ -96,10 +102,34 @@ def fp8_configs():
     return _lp_configs(FP8_K_TILES, 1) + _lp_small_configs(FP8_SMALL_K_TILES)
 
 
+SPLIT_EDGES = (16, 32, 64, 128)
+SPLIT_SLICES = (2, 4, 8, 16)
+
+
+def split_variants(cfgs):
+    """Split-K variants of a configuration list, as (base id, slices): for
+    each square work-group tile edge in SPLIT_EDGES, the configuration with
+    the deepest K tile and, among those, the most waves (smallest t), run
+    over 2, 4, 8 and 16 slices."""
+    out = []
+    for e in SPLIT_EDGES:
+        cand = [(i, c) for i, c in enumerate(cfgs) if c[0] == e and c[1] == e]
+        if not cand:
+            continue
+        base = min(cand, key=lambda ic: (-ic[1][3], ic[1][2], ic[0]))[0]
+        out += [(base, s) for s in SPLIT_SLICES]
+    return out
+
+
+def kernels(cfgs):
+    """(bm, bn, t, bk, slices) per kernel id: configurations, then split-K variants."""
+    return [tuple(c) + (1,) for c in cfgs] + [tuple(cfgs[b]) + (s,) for (b, s) in split_variants(cfgs)]
+
+
 DTYPES = (  # (name, config list, launcher template)
     ("f32", f32_configs, "launch_gemm_f32<{bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_f32.hpp"),
-    ("bf16", bf16_configs, "launch_gemm_lp<2, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
-    ("fp8", fp8_configs, "launch_gemm_lp<1, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp.hpp"),
+    ("bf16", bf16_configs, "launch_gemm_lp<2, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp_dma.hpp"),
+    ("fp8", fp8_configs, "launch_gemm_lp<1, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp_dma.hpp"),
 )
 
 
@@ -143,13 +173,19 @@ def generate(out_dir: str, f32_ids=None, lp_ids=None, n_parts: int = 24, lp_part
         for (bm, bn, t, bk) in cfgs:
             reg.append(f"  {{{bm}, {bn}, {t}, {bk}}},")
         reg.append("};")
+        splits = split_variants(cfgs)
+        reg.append(f"static const SplitDef {name}_splits[] = {{")
+        for (b, sl) in splits:
+            reg.append(f"  {{{b}, {sl}}},")
+        reg.append("};")
         reg.append(f"static const PartRef {name}_parts[] = {{")
         for p in range(len(parts)):
             reg.append(f"  {{{name}_part{p}, &{name}_part{p}_n}},")
         if not parts:
             reg.append("  {nullptr, nullptr},")
         reg.append("};")
-        tables.append(f"  {{{name}_configs, {len(cfgs)}, {name}_parts, {len(parts)}}},")
+        tables.append(f"  {{{name}_configs, {len(cfgs)}, {name}_splits, {len(splits)}, "
+                      f"{name}_parts, {len(parts)}}},")
     reg.append("const DtypeRegistry dtype_registry[3] = {")
     reg += tables
     reg.append("};")
@@ -172,3 +208,6 @@ if __name__ == "__main__":
     by_t = {t: sum(1 for x in c if x[2] == t) for t in THREAD_TILES}
     print("f32", len(c), by_t)
     print("bf16", len(bf16_configs()), "fp8", len(fp8_configs()))
+    for name, fn in (("f32", f32_configs), ("bf16", bf16_configs), ("fp8", fp8_configs)):
+        cf = fn()
+        print(name, "split-K bases", sorted({cf[b] for (b, _) in split_variants(cf)}))

@@ -41,6 +41,7 @@ static void build_tables(Ctx* h) {
   for (int d = 0; d < NUM_DTYPES; ++d) {
     const DtypeRegistry& r = dtype_registry[d];
     h->configs[d].assign(r.configs, r.configs + r.n_configs);
+    h->splits[d].assign(r.splits, r.splits + r.n_splits);
     h->table[d].assign((size_t)r.n_configs * 4, nullptr);
     for (int p = 0; p < r.n_parts; ++p) {
       const PartRef& pr = r.parts[p];
@@ -78,6 +79,25 @@ kt_status check_gemm_args(Ctx* h, const kt_shape* s, int64_t lda, int64_t sA, in
 
 static int elem_bytes(int dtype) { return dtype == KT_F32 ? 4 : dtype == KT_BF16 ? 2 : 1; }
 
+// Row alignment of an operand for the low-precision loaders: 2 = every row
+// starts on a 4-byte boundary, 1 = only the base pointer does (rows are then
+// loaded through a realigned window), 0 = neither (element loads); 3 = every
+// row on a 16-byte boundary and whole 16-byte chunks along the contiguous
+// extent `ext` (K for an operand stored K-contiguous, M or N otherwise),
+// which takes the low-precision DMA pipeline.  FP32 rows are always 4-byte
+// aligned (2).
+int32_t operand_alignment(int dtype, const void* p, int64_t ld, int64_t stride, int64_t batch,
+                          int64_t ext) {
+  const int eb = elem_bytes(dtype);
+  if ((uintptr_t)p % 4 != 0) return 0;
+  if ((ld * eb) % 4 != 0 || (stride * eb) % 4 != 0) return 1;
+  const int64_t ce = 16 / eb;
+  if (eb < 4 && (uintptr_t)p % 16 == 0 && ld % ce == 0 && (batch <= 1 || stride % ce == 0) &&
+      ext % ce == 0)
+    return 3;
+  return 2;
+}
+
 kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const void* A,
                       int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB,
                       float beta, float* C, int64_t ldc, int64_t sC, const float* scaleA,
@@ -92,23 +112,14 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
   const ConfigDef& c = h->configs[dtype][cfg];
   const int64_t tiles = cdiv(s->M, c.bm) * cdiv(s->N, c.bn);
   if (tiles > 0x7fffffffLL) return fail(h, KT_EINVAL, "problem too large for one grid");
-  const int eb = elem_bytes(dtype);
-  // Row alignment of an operand for the low-precision loaders: 2 = every row
-  // starts on a 4-byte boundary, 1 = only the base pointer does (rows are then
-  // loaded through a realigned window), 0 = neither (element loads).  FP32
-  // rows are always 4-byte aligned.
-  auto aligned = [&](const void* p, int64_t ld, int64_t st) -> int32_t {
-    if ((uintptr_t)p % 4 != 0) return 0;
-    return ((ld * eb) % 4 == 0 && (st * eb) % 4 == 0) ? 2 : 1;
-  };
   GemmArgs g;
   memset(&g, 0, sizeof g);
   g.M = s->M; g.N = s->N; g.K = s->K;
   g.lda = lda; g.sA = sA; g.ldb = ldb; g.sB = sB; g.ldc = ldc; g.sC = sC;
   g.alpha = alpha; g.beta = beta;
   g.scaleA = scaleA; g.scaleB = scaleB;
-  g.vecA = aligned(A, lda, sA);
-  g.vecB = aligned(B, ldb, sB);
+  g.vecA = operand_alignment(dtype, A, lda, sA, s->batch, s->transA ? s->M : s->K);
+  g.vecB = operand_alignment(dtype, B, ldb, sB, s->batch, s->transB ? s->K : s->N);
   g.batch = s->batch;
   g.A = A;
   g.B = B;
@@ -124,7 +135,7 @@ using namespace kt;
 
 extern "C" {
 
-int32_t kt_abi_version(void) { return 100; }
+int32_t kt_abi_version(void) { return 110; }
 
 kt_status kt_create(kt_handle* out, int device) {
   if (!out) return fail(nullptr, KT_EINVAL, "out is NULL");
@@ -215,7 +226,50 @@ kt_status kt_config_compiled(kt_handle hh, kt_dtype dtype, int32_t id, int32_t t
                              int32_t* compiled) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h || !compiled) return fail(h, KT_EINVAL, "NULL argument");
-  *compiled = find_launcher(h, dtype, id, ta, tb) != nullptr;
+  *compiled = valid_kernel(h, dtype, id) &&
+              find_launcher(h, dtype, kernel_base(h, dtype, id), ta, tb) != nullptr;
+  return KT_OK;
+}
+
+kt_status kt_num_kernels(kt_handle hh, kt_dtype dtype, int32_t* n) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h || !n) return fail(h, KT_EINVAL, "NULL argument");
+  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
+  *n = num_kernels(h, dtype);
+  return KT_OK;
+}
+
+kt_status kt_get_kernel(kt_handle hh, kt_dtype dtype, int32_t id, kt_config* cfg, int32_t* base_id,
+                        int32_t* slices) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h || !cfg || !base_id || !slices) return fail(h, KT_EINVAL, "NULL argument");
+  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
+  if (!valid_kernel(h, dtype, id)) return fail(h, KT_EINVAL, "kernel id out of range");
+  *base_id = kernel_base(h, dtype, id);
+  *slices = kernel_slices(h, dtype, id);
+  const ConfigDef& c = h->configs[dtype][*base_id];
+  cfg->bm = c.bm; cfg->bn = c.bn; cfg->t = c.t; cfg->bk = c.bk; cfg->dtype = dtype;
+  return KT_OK;
+}
+
+kt_status kt_set_workspace(kt_handle hh, void* workspace, size_t bytes) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!workspace && bytes) return fail(h, KT_EINVAL, "NULL workspace with a nonzero size");
+  h->gemm_ws = workspace;
+  h->gemm_ws_bytes = workspace ? bytes : 0;
+  return KT_OK;
+}
+
+kt_status kt_kernel_workspace_bytes(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_t id,
+                                    size_t* bytes) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h || !s || !bytes) return fail(h, KT_EINVAL, "NULL argument");
+  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
+  if (!valid_kernel(h, dtype, id)) return fail(h, KT_EINVAL, "kernel id out of range");
+  if (s->M < 0 || s->N < 0 || s->K < 0 || s->batch < 0)
+    return fail(h, KT_EINVAL, "negative M, N, K or batch");
+  *bytes = kernel_plane_bytes(h, dtype, s, id);
   return KT_OK;
 }
 
@@ -234,15 +288,25 @@ kt_status kt_gemm(kt_handle hh, kt_dtype in_dtype, const kt_shape* s, float alph
   if (s->K > 0 && (!A || !B)) return fail(h, KT_EINVAL, "A or B is NULL");
   if (in_dtype == KT_FP8E4M3 && (!scaleA || !scaleB))
     return fail(h, KT_EINVAL, "FP8 needs device scale pointers");
-  int32_t cfg = config_id;
-  if (cfg < 0) {
-    st = select_config(h, in_dtype, s, &cfg);
+  int32_t id = config_id;
+  if (id < 0) {
+    st = select_config(h, in_dtype, s, &id);
     if (st != KT_OK) return st;
   }
-  if (cfg >= (int32_t)h->configs[in_dtype].size())
-    return fail(h, KT_EINVAL, "config id out of range");
-  return launch_gemm(h, in_dtype, s, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc,
-                     strideC, scaleA, scaleB, cfg, (hipStream_t)stream);
+  if (!valid_kernel(h, in_dtype, id)) return fail(h, KT_EINVAL, "kernel id out of range");
+  return run_kernel(h, in_dtype, s, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc,
+                    strideC, scaleA, scaleB, id, h->gemm_ws, h->gemm_ws_bytes, (hipStream_t)stream);
+}
+
+kt_status kt_lp_pipeline(kt_dtype dtype, const kt_shape* s, const void* A, int64_t lda,
+                         int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+                         int32_t* dma) {
+  if (!s || !dma) return fail(nullptr, KT_EINVAL, "NULL argument");
+  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(nullptr, KT_EINVAL, "bad dtype");
+  *dma = dtype != KT_F32 &&
+         operand_alignment(dtype, A, lda, strideA, s->batch, s->transA ? s->M : s->K) == 3 &&
+         operand_alignment(dtype, B, ldb, strideB, s->batch, s->transB ? s->K : s->N) == 3;
+  return KT_OK;
 }
 
 kt_status kt_fill_uniform(kt_handle hh, float* dst, int64_t n, uint64_t seed, int64_t offset,

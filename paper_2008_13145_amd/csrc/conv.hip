@@ -322,7 +322,10 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
     bool fused = false;   // bias and activation applied by the split-K reduction
     if (splits == 1) {
       int32_t cfg = config_id;
-      if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
+      if (cfg < 0) {   // the selected kernel's configuration (the layer's split is `splits`)
+        if ((st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
+        cfg = kernel_base(h, KT_F32, cfg);
+      }
       st = launch_gemm(h, KT_F32, &gs, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O, 0.f, y,
                        d.O, gs.M * d.O, nullptr, nullptr, cfg, s);
     } else {
@@ -340,7 +343,10 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
     return KT_OK;
   }
   int32_t cfg = config_id;
-  if (cfg < 0 && (st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
+  if (cfg < 0) {
+    if ((st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
+    cfg = kernel_base(h, KT_F32, cfg);
+  }
   const int64_t tH = (d.Ho + 1) / 2, tW = (d.Wo + 1) / 2, T = gs.M;
   const bool pre = algo == KT_CONV_WINOGRAD_PRETRANSFORMED;   // w already holds U
   float* V = (float*)ws;

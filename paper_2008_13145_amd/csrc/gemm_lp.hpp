@@ -475,10 +475,4 @@ gemm_lp_kernel(GemmArgs args) {
   lp_tile<EB, BM, BN, T, BK, TA, TB>(args, tm, tn, bz, lds);
 }
 
-template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
-hipError_t launch_gemm_lp(const GemmArgs& a, hipStream_t stream) {
-  using Cfg = GemmLpCfg<EB, BM, BN, T, BK, TA, TB>;
-  return launch_flat<EB>(gemm_lp_kernel<EB, BM, BN, T, BK, TA, TB>, a, BM, BN, Cfg::NT, stream);
-}
-
 }  // namespace kt

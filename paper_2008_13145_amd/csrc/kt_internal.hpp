@@ -60,6 +60,7 @@ struct Ctx {
   // launcher lookup: [dtype][id * 4 + layout]
   std::vector<LaunchFn> table[NUM_DTYPES];
   std::vector<ConfigDef> configs[NUM_DTYPES];
+  std::vector<SplitDef> splits[NUM_DTYPES];   // split-K variants after the configurations
   SelState sel[NUM_DTYPES];
   void* scratch = nullptr;         // exhaustive-selection operands (handle-owned)
   size_t scratch_bytes = 0;
@@ -67,6 +68,8 @@ struct Ctx {
   void* d_lut = nullptr;           // device sigmoid table (handle-owned)
   kt_grouped_opts grouped_best{};  // autotuner result for grouped GEMM
   bool grouped_tuned = false;
+  void* gemm_ws = nullptr;         // caller's workspace for split-K kernels run by kt_gemm
+  size_t gemm_ws_bytes = 0;
   void* noalloc_scratch = nullptr; // device address of the static split-K scratch
   bool forbid_alloc = false;       // set while an entry point that must not allocate runs
 };
@@ -86,6 +89,45 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
                       int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB,
                       float beta, float* C, int64_t ldc, int64_t sC, const float* scaleA,
                       const float* scaleB, int32_t cfg, hipStream_t stream);
+
+// Alignment class of an operand (GemmArgs::vecA / vecB).
+int32_t operand_alignment(int dtype, const void* p, int64_t ld, int64_t stride, int64_t batch,
+                          int64_t ext);
+
+// Kernel ids: configurations 0 .. n_configs-1, then split-K variants.
+inline int32_t num_kernels(const Ctx* h, int dtype) {
+  return (int32_t)(h->configs[dtype].size() + h->splits[dtype].size());
+}
+inline bool valid_kernel(const Ctx* h, int dtype, int32_t id) {
+  return dtype >= 0 && dtype < NUM_DTYPES && id >= 0 && id < num_kernels(h, dtype);
+}
+// The configuration a kernel runs (the kernel itself, or a variant's base).
+inline int32_t kernel_base(const Ctx* h, int dtype, int32_t id) {
+  const int32_t nc = (int32_t)h->configs[dtype].size();
+  return id < nc ? id : h->splits[dtype][id - nc].base;
+}
+inline int32_t kernel_slices(const Ctx* h, int dtype, int32_t id) {
+  const int32_t nc = (int32_t)h->configs[dtype].size();
+  return id < nc ? 1 : h->splits[dtype][id - nc].slices;
+}
+
+// Partial planes of a split-K kernel never exceed this (beyond it, or beyond
+// the workspace at hand, the variant runs as its base configuration unsplit).
+constexpr size_t SPLIT_PLANE_CAP = (size_t)256 << 20;
+
+// Bytes of partial planes kernel `id` uses on shape s (0 when it runs unsplit
+// with an unlimited workspace).
+size_t kernel_plane_bytes(const Ctx* h, int dtype, const kt_shape* s, int32_t id);
+// The same for a slice count (no handle needed).
+size_t split_plane_bytes(const kt_shape* s, int32_t slices);
+
+// Run kernel `id` (a configuration or a split-K variant; the variant gets
+// the workspace [ws, ws + ws_bytes) for its partial planes and runs unsplit
+// when they do not fit).  No validation beyond lookup.
+kt_status run_kernel(Ctx* h, int dtype, const kt_shape* s, float alpha, const void* A,
+                     int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB, float beta,
+                     float* C, int64_t ldc, int64_t sC, const float* scaleA, const float* scaleB,
+                     int32_t id, void* ws, size_t ws_bytes, hipStream_t stream);
 
 // Fill kernel launcher (device).
 hipError_t fill_uniform(float* dst, int64_t n, uint64_t seed, int64_t offset, hipStream_t s);

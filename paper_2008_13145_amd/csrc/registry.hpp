@@ -20,6 +20,11 @@ struct ConfigDef {
   int32_t bm, bn, t, bk;
 };
 
+// A split-K variant: configuration `base` run over `slices` slices of K.
+struct SplitDef {
+  int32_t base, slices;
+};
+
 struct PartRef {
   LaunchEntry* entries;
   const int* count;
@@ -28,6 +33,8 @@ struct PartRef {
 struct DtypeRegistry {
   const ConfigDef* configs;   // the configuration space of the dtype (id = index)
   int n_configs;
+  const SplitDef* splits;     // split-K variants (kernel id = n_configs + index)
+  int n_splits;
   const PartRef* parts;       // compiled instantiations
   int n_parts;
 };

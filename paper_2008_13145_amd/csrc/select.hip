@@ -193,10 +193,11 @@ static kt_status upload_tree(Ctx* h, int dtype) {
 
 static int64_t elem_bytes_sel(int dtype) { return dtype == KT_F32 ? 4 : dtype == KT_BF16 ? 2 : 1; }
 
-// Time the candidate configurations (those compiled for the shape's layout)
-// on handle-owned scratch operands (generated in FP32 and converted for
-// BF16 / FP8): one untimed launch, then three timed ones each; the fastest
-// (first on ties) wins.  Allocates the scratch on first use and synchronizes.
+// Time the candidate kernels (those whose configuration is compiled for the
+// shape's layout) on handle-owned scratch operands (generated in FP32 and
+// converted for BF16 / FP8), split-K variants with scratch partial planes:
+// one untimed launch, then three timed ones each; the fastest (first on
+// ties) wins.  Allocates the scratch on first use and synchronizes.
 static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
                                  const std::vector<int32_t>& cands, int32_t* out) {
   if (!need_device(h)) return KT_EINVAL;
@@ -213,7 +214,10 @@ static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
   auto r256 = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
   const int64_t offB = r256(nA * eb), offC = offB + r256(nB * eb), offS = offC + r256(nC * 4);
   const int64_t offT = offS + 256;   // FP32 staging for BF16 / FP8 operands
-  const size_t need = (size_t)(offT + (dtype == KT_F32 ? 0 : std::max(nA, nB) * 4) + 256);
+  const int64_t offW = offT + r256(dtype == KT_F32 ? 0 : std::max(nA, nB) * 4);   // split-K planes
+  size_t planes = 0;
+  for (int32_t id : cands) planes = std::max(planes, kernel_plane_bytes(h, dtype, s, id));
+  const size_t need = (size_t)offW + planes + 256;
   if (h->scratch_bytes < need) {
     if (h->scratch) (void)hipFree(h->scratch);
     h->scratch = nullptr;
@@ -254,10 +258,10 @@ static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
   kt_status st = KT_OK;
   for (size_t ci = 0; ci < cands.size() && st == KT_OK; ++ci) {
     const int32_t id = cands[ci];
-    if (!find_launcher(h, dtype, id, s->transA, s->transB)) continue;
+    if (!find_launcher(h, dtype, kernel_base(h, dtype, id), s->transA, s->transB)) continue;
     auto launch = [&]() {
-      return launch_gemm(h, dtype, s, 1.f, A, lda, a_rows * lda, B, ldb, b_rows * ldb, 0.f, C, ldc,
-                         s->M * ldc, scales, scales + 1, id, nullptr);
+      return run_kernel(h, dtype, s, 1.f, A, lda, a_rows * lda, B, ldb, b_rows * ldb, 0.f, C, ldc,
+                        s->M * ldc, scales, scales + 1, id, base + offW, planes, nullptr);
     };
     if ((st = launch()) != KT_OK) break;
     (void)hipEventRecord(e0, nullptr);
@@ -276,13 +280,14 @@ static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
   return KT_OK;
 }
 
-// Exhaustive selection: every configuration of the dtype, cached per shape.
+// Exhaustive selection: every kernel of the dtype (configurations and split-K
+// variants), cached per shape.
 static kt_status exhaustive_select(Ctx* h, int dtype, const kt_shape* s, int32_t* out) {
   SelState& S = h->sel[dtype];
   const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, dtype};
   auto it = S.exhaustive_cache.find(key);
   if (it != S.exhaustive_cache.end()) { *out = it->second; return KT_OK; }
-  std::vector<int32_t> all(h->configs[dtype].size());
+  std::vector<int32_t> all(num_kernels(h, dtype));
   std::iota(all.begin(), all.end(), 0);
   kt_status st = time_candidates(h, dtype, s, all, out);
   if (st == KT_OK) S.exhaustive_cache[key] = *out;
@@ -308,13 +313,22 @@ static void set_box(SelState& S, const kt_shape* shapes, int32_t n) {
 }
 
 // Fallback for a shape outside the training box: the fastest of the chosen
-// configurations, timed once and cached.
+// kernels and of the split-K variants of their configurations (code the
+// deployed set already holds), timed once and cached.
 static kt_status fallback_select(Ctx* h, int dtype, const kt_shape* s, int32_t* out) {
   SelState& S = h->sel[dtype];
   const ShapeKey key{s->M, s->N, s->K, s->batch, s->transA, s->transB, dtype};
   auto it = S.fallback_cache.find(key);
   if (it != S.fallback_cache.end()) { *out = it->second; return KT_OK; }
-  kt_status st = time_candidates(h, dtype, s, S.chosen, out);
+  std::vector<int32_t> cands = S.chosen;
+  const int32_t nc = (int32_t)h->configs[dtype].size();
+  for (int32_t v = nc; v < num_kernels(h, dtype); ++v) {
+    const int32_t b = kernel_base(h, dtype, v);
+    bool have_base = false;
+    for (int32_t c : S.chosen) have_base = have_base || kernel_base(h, dtype, c) == b;
+    if (have_base && std::find(cands.begin(), cands.end(), v) == cands.end()) cands.push_back(v);
+  }
+  kt_status st = time_candidates(h, dtype, s, cands, out);
   if (st == KT_OK) S.fallback_cache[key] = *out;
   return st;
 }
@@ -378,7 +392,7 @@ kt_status kt_fit_selector(kt_handle hh, kt_dtype dtype, kt_selector sel, const k
   if (n < 1 || d < 1 || !shapes || !time_ns || !chosen || k < 1 || k > d)
     return fail(h, KT_EINVAL, "bad training data");
   for (int32_t j = 0; j < k; ++j) {
-    if (chosen[j] < 0 || chosen[j] >= d || chosen[j] >= (int32_t)h->configs[dtype].size())
+    if (chosen[j] < 0 || chosen[j] >= d || !valid_kernel(h, dtype, chosen[j]))
       return fail(h, KT_EINVAL, "chosen id out of range");
     for (int32_t q = 0; q < j; ++q)
       if (chosen[q] == chosen[j]) return fail(h, KT_EINVAL, "chosen ids must be distinct");
@@ -555,7 +569,7 @@ kt_status kt_load(kt_handle hh, const char* path) {
     if (!(in >> tag >> k) || tag != "chosen" || k > 4096) return bad("chosen");
     L.chosen.resize(k);
     for (size_t j = 0; j < k; ++j)
-      if (!(in >> L.chosen[j]) || L.chosen[j] < 0 || L.chosen[j] >= (int32_t)h->configs[L.dtype].size())
+      if (!(in >> L.chosen[j]) || !valid_kernel(h, L.dtype, L.chosen[j]))
         return bad("chosen id");
     size_t nn = 0;
     if (!(in >> tag >> nn) || tag != "tree" || nn > (1u << 24)) return bad("tree");

@@ -116,6 +116,40 @@ kt_status kt_gemm_splitk(kt_handle hh, kt_dtype dtype, const kt_shape* s, int32_
 
 namespace kt {
 
+// Slices a split-K variant really uses on shape s (slice depths are whole
+// multiples of 64, so a shallow K takes fewer slices than asked for).
+static int32_t effective_slices(const kt_shape* s, int32_t slices) {
+  if (slices <= 1 || s->K <= 0) return 1;
+  return (int32_t)cdiv(s->K, slice_depth(s->K, slices));
+}
+
+size_t split_plane_bytes(const kt_shape* s, int32_t slices) {
+  const int32_t S = effective_slices(s, slices);
+  if (S <= 1) return 0;
+  const size_t need = a256((size_t)S * plane_bytes(s));
+  return need <= SPLIT_PLANE_CAP ? need : 0;
+}
+
+size_t kernel_plane_bytes(const Ctx* h, int dtype, const kt_shape* s, int32_t id) {
+  return split_plane_bytes(s, kernel_slices(h, dtype, id));
+}
+
+kt_status run_kernel(Ctx* h, int dtype, const kt_shape* s, float alpha, const void* A,
+                     int64_t lda, int64_t sA, const void* B, int64_t ldb, int64_t sB, float beta,
+                     float* C, int64_t ldc, int64_t sC, const float* scaleA, const float* scaleB,
+                     int32_t id, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!valid_kernel(h, dtype, id))
+    return fail(h, KT_EINVAL, "kernel id " + std::to_string(id) + " out of range");
+  const int32_t base = kernel_base(h, dtype, id);
+  const size_t need = kernel_plane_bytes(h, dtype, s, id);
+  if (need == 0 || !ws || ws_bytes < need || s->M == 0 || s->N == 0 || s->batch == 0)
+    return launch_gemm(h, dtype, s, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, scaleA,
+                       scaleB, base, stream);
+  return splitk_gemm(h, (kt_dtype)dtype, s, kernel_slices(h, dtype, id), alpha, A, lda, sA, B,
+                     ldb, sB, beta, C, ldc, sC, scaleA, scaleB, base, ws, ws_bytes, stream,
+                     nullptr, nullptr, 0, nullptr);
+}
+
 kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits, float alpha,
                       const void* A, int64_t lda, int64_t strideA, const void* B, int64_t ldb,
                       int64_t strideB, float beta, float* C, int64_t ldc, int64_t strideC,
@@ -141,7 +175,10 @@ kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits,
 
   const int64_t K = s->K;
   if (splits == 0) {   // automatic: the configuration first (selector on the whole product)
-    if (config_id < 0 && (st = select_config(h, dtype, s, &config_id)) != KT_OK) return st;
+    if (config_id < 0) {
+      if ((st = select_config(h, dtype, s, &config_id)) != KT_OK) return st;
+      config_id = kernel_base(h, dtype, config_id);
+    }
     const ConfigDef& c = h->configs[dtype][config_id];
     splits = auto_splits(cdiv(s->M, c.bm) * cdiv(s->N, c.bn) * s->batch, K);
   }
@@ -149,7 +186,10 @@ kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits,
   const int32_t S = K > 0 ? (int32_t)cdiv(K, kc) : 1;
   if (S <= 1) {   // one slice: the plain product, no workspace
     int32_t cfg = config_id;
-    if (cfg < 0 && (st = select_config(h, dtype, s, &cfg)) != KT_OK) return st;
+    if (cfg < 0) {
+      if ((st = select_config(h, dtype, s, &cfg)) != KT_OK) return st;
+      cfg = kernel_base(h, dtype, cfg);
+    }
     return launch_gemm(h, dtype, s, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc,
                        strideC, scaleA, scaleB, cfg, stream_h);
   }
@@ -165,6 +205,7 @@ kt_status splitk_gemm(Ctx* h, kt_dtype dtype, const kt_shape* s, int32_t splits,
     ps.K = kc;
     ps.batch = s->batch * S;
     if ((st = select_config(h, dtype, &ps, &cfg)) != KT_OK) return st;
+    cfg = kernel_base(h, dtype, cfg);
   }
   const int eb = dtype == KT_F32 ? 4 : dtype == KT_BF16 ? 2 : 1;
   // element offsets of one slice depth along K in A and B

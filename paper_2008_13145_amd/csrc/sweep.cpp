@@ -1,6 +1,7 @@
 // Exhaustive configuration sweep (sections 3 and 3.1 of the paper): every
-// configuration is benchmarked on every problem -- a few warm-up launches,
-// then a timed loop sized to a target duration, mean time per launch.
+// kernel (configuration or split-K variant) is benchmarked on every problem
+// -- a few warm-up launches, then a timed loop sized to a target duration,
+// mean time per launch.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -83,6 +84,14 @@ using namespace kt;
 
 extern "C" {
 
+// Largest partial-plane need of any split-K variant of the dtype on shape s.
+static size_t max_split_planes(int dtype, const kt_shape& s) {
+  const DtypeRegistry& r = dtype_registry[dtype];
+  size_t m = 0;
+  for (int i = 0; i < r.n_splits; ++i) m = std::max(m, split_plane_bytes(&s, r.splits[i].slices));
+  return m;
+}
+
 kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_dtype dtype,
                                    size_t* bytes) {
   if (!bytes || (n_shapes > 0 && !shapes) || n_shapes < 0) return KT_EINVAL;
@@ -90,7 +99,7 @@ kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_
   size_t m = 0;
   for (int32_t i = 0; i < n_shapes; ++i) {
     if (shapes[i].M < 0 || shapes[i].N < 0 || shapes[i].K < 0 || shapes[i].batch < 0) return KT_EINVAL;
-    m = std::max(m, plan_for(shapes[i], dtype).total);
+    m = std::max(m, plan_for(shapes[i], dtype).total + max_split_planes(dtype, shapes[i]));
   }
   *bytes = m;
   return KT_OK;
@@ -110,21 +119,24 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
     if (n_configs < 0) return fail(h, KT_EINVAL, "n_configs < 0");
     ids.assign(config_ids, config_ids + n_configs);
   } else {
-    ids.resize(h->configs[dtype].size());
+    ids.resize(num_kernels(h, dtype));
     std::iota(ids.begin(), ids.end(), 0);
     n_configs = (int32_t)ids.size();
   }
   for (int32_t id : ids)
-    if (id < 0 || id >= (int32_t)h->configs[dtype].size()) return fail(h, KT_EINVAL, "config id out of range");
+    if (!valid_kernel(h, dtype, id)) return fail(h, KT_EINVAL, "kernel id out of range");
   if (opts->min_reps < 1 || opts->max_reps < opts->min_reps || opts->warmup < 0 || opts->target_ms < 0)
     return fail(h, KT_EINVAL, "bad sweep options");
   hipStream_t stream = (hipStream_t)stream_v;
-  // Visit large work-group tiles first so the early cut has a tight reference.
+  // Visit large work-group tiles first so the early cut has a tight
+  // reference; split-K variants after every configuration.
   std::vector<int> order(ids.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const ConfigDef& ca = h->configs[dtype][ids[a]];
-    const ConfigDef& cb = h->configs[dtype][ids[b]];
+    const int32_t sa = kernel_slices(h, dtype, ids[a]), sb = kernel_slices(h, dtype, ids[b]);
+    if ((sa > 1) != (sb > 1)) return sb > 1;
+    const ConfigDef& ca = h->configs[dtype][kernel_base(h, dtype, ids[a])];
+    const ConfigDef& cb = h->configs[dtype][kernel_base(h, dtype, ids[b])];
     const int64_t wa = (int64_t)ca.bm * ca.bn, wb = (int64_t)cb.bm * cb.bn;
     if (wa != wb) return wa > wb;
     return ca.t > cb.t;
@@ -142,7 +154,12 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
     for (int32_t c = 0; c < n_configs; ++c) done = done && row[c] >= 0;
     if (done) continue;
     OperandPlan p = plan_for(s, dtype);
-    if (!workspace || ws_bytes < p.total) { result = fail(h, KT_EWORKSPACE, "sweep workspace too small"); break; }
+    size_t planes = 0;   // partial planes of the split-K kernels in the list
+    for (int32_t id : ids) planes = std::max(planes, kernel_plane_bytes(h, dtype, &s, id));
+    if (!workspace || ws_bytes < p.total + planes) {
+      result = fail(h, KT_EWORKSPACE, "sweep workspace too small");
+      break;
+    }
     char* ws = (char*)workspace;
     const void* A = ws + p.offA;
     const void* B = ws + p.offB;
@@ -161,8 +178,8 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
       if (row[c] >= 0) continue;
       const int32_t id = ids[c];
       auto launch = [&]() {
-        return launch_gemm(h, dtype, &s, opts->alpha, A, p.lda, p.sA, B, p.ldb, p.sB,
-                           opts->beta, C, p.ldc, p.sC, scales, scales + 1, id, stream);
+        return run_kernel(h, dtype, &s, opts->alpha, A, p.lda, p.sA, B, p.ldb, p.sB, opts->beta,
+                          C, p.ldc, p.sC, scales, scales + 1, id, ws + p.total, planes, stream);
       };
       for (int w = 0; w < opts->warmup && result == KT_OK; ++w) result = launch();
       if (result != KT_OK) break;

@@ -106,10 +106,15 @@ def pca_pruning(h, T_train, k, seed, dims, norm, rep=2, n_init=10, max_iter=300,
 
 
 def load_table(path):
-    """(time_ns int64 [P][C], problems int64 [P][6], configs int32 [C][4], meta dict)."""
+    """(time_ns int64 [P][C], problems int64 [P][6], kernels int32 [C][5], meta
+    dict).  Column c is kernel id c; a kernel row is (bm, bn, t, bk, slices)
+    (tables that hold configurations only have slices 1 added)."""
     with np.load(path, allow_pickle=False) as z:
         meta = json.loads(str(z["meta"]))
-        return z["time_ns"].copy(), z["problems"].copy(), z["configs"].copy(), meta
+        C = z["configs"].copy()
+        if C.shape[1] == 4:
+            C = np.concatenate([C, np.ones((C.shape[0], 1), C.dtype)], axis=1)
+        return z["time_ns"].copy(), z["problems"].copy(), C, meta
 
 
 def save_table(path, time_ns, problems, configs, meta):
@@ -120,8 +125,8 @@ def save_table(path, time_ns, problems, configs, meta):
     os.replace(tmp, path)
 
 
-def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
-              cut_factor=8.0, warmup=0, limit=None, log=print, dtype=0, set_name="sweep"):
+def run_sweep(out, budget_s=900.0, target_ms=5.0, min_reps=3, max_reps=200,
+              cut_factor=8.0, warmup=2, limit=None, log=print, dtype=0, set_name="sweep"):
     import torch
 
     import synth
@@ -130,7 +135,7 @@ def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
     problems = problem_set(set_name)
     if limit:
         problems = problems[:limit]
-    configs = h.configs(dtype)
+    configs = h.kernels(dtype)     # every kernel: configurations, then split-K variants
     if os.path.exists(out):
         T, P, C, meta = load_table(out)
         if P.tolist() != [list(p) for p in problems] or C.tolist() != [list(c) for c in configs]:
@@ -144,6 +149,7 @@ def run_sweep(out, budget_s=900.0, target_ms=1.5, min_reps=3, max_reps=100,
                     seed=synth.SEED, started=time.time(), seconds=0.0, dtype=dtype)
     ws_bytes = Handle.sweep_workspace_bytes(problems, dtype)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
     # Load every kernel once on a tiny problem, so that no row pays for code
     # object loading and the first timed launch of a pair is representative.
     tiny = [(8, 8, 8, 1, ta, tb) for (ta, tb) in synth.LAYOUTS]
@@ -211,7 +217,8 @@ def main(argv=None):
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         res = select_pruning(h, T[rows], a.k, synth.SEED, workspace=ws, ws_bytes=ws_bytes)
         chosen = res["chosen"]
-        spec = dict(dtype="f32", k=a.k, chosen=chosen, configs=[list(map(int, C[i])) for i in chosen],
+        spec = dict(dtype="f32", k=a.k, chosen=chosen, kernels=[list(map(int, C[i])) for i in chosen],
+                    config_ids=sorted({h.get_kernel(c)[1] for c in chosen}),
                     norm=res["norm_name"], train_ceiling=res["train_ceiling"], seed=synth.SEED,
                     n_init=10, max_iter=300, table=os.path.relpath(a.table, HERE),
                     device=meta.get("device"), inertia=res["inertia"])
@@ -220,7 +227,8 @@ def main(argv=None):
             json.dump(spec, f, indent=1)
         print("chosen", chosen, spec["configs"], flush=True)
         if not a.no_build:
-            build.build(f32_ids=chosen, lp_ids=[], out=a.out, tag="deploy", verbose=True)
+            build.build(f32_ids=spec["config_ids"], lp_ids=[], out=a.out, tag="deploy",
+                        verbose=True)
     return 0
 
 

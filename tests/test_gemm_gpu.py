@@ -219,7 +219,8 @@ def test_invalid_arguments(gpu):
     for shp, lda, ldb, ldc, want in cases:
         st = h.gemm_raw(0, shp, 1.0, d, lda, 16, d, ldb, 16, 0.0, d, ldc, 16, config_id=0, check=False)
         assert st == want
-    st = h.gemm_raw(0, kt.shape(4, 4, 4), 1.0, d, 4, 0, d, 4, 0, 0.0, d, 4, 0, config_id=164, check=False)
+    st = h.gemm_raw(0, kt.shape(4, 4, 4), 1.0, d, 4, 0, d, 4, 0, 0.0, d, 4, 0,
+                    config_id=h.num_kernels(), check=False)
     assert st == -1
     st = h.gemm_raw(0, kt.shape(4, 4, 4), 1.0, d, 4, 0, d, 4, 0, 0.0, d, 4, 0, config_id=-1, check=False)
     assert st == -4            # no selector fitted yet

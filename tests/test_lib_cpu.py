@@ -81,6 +81,8 @@ def test_host_handle_rejects_gpu_work(kt):
     with pytest.raises(kt.KtError):
         h.get_config(164)
     with pytest.raises(kt.KtError):
+        h.get_kernel(-1)
+    with pytest.raises(kt.KtError):
         h.get_config(-1)
 
 
@@ -90,7 +92,38 @@ def test_create_rejects_bad_device(kt):
 
 
 def test_abi_version(kt):
-    assert kt.lib().kt_abi_version() == 100
+    assert kt.lib().kt_abi_version() == 110
+
+
+def test_kernel_ids(kt):
+    """Kernels = configurations, then the split-K variants the generator
+    defines (per square tile edge 16..128: deepest K tile, then most waves;
+    slices 2, 4, 8, 16); out-of-range ids are refused; the workspace a
+    variant needs follows its slices and the 256 MiB cap."""
+    from paper_2008_13145_amd import codegen
+    h = kt.Handle(-1)
+    for dt, gen in ((kt.F32, codegen.f32_configs), (kt.BF16, codegen.bf16_configs),
+                    (kt.FP8E4M3, codegen.fp8_configs)):
+        cfgs = gen()
+        ks = h.kernels(dt)
+        assert ks == codegen.kernels(cfgs) and len(ks) == len(cfgs) + 16
+        for v in range(len(cfgs), len(ks)):
+            k, base = h.get_kernel(v, dt)
+            assert k[:4] == cfgs[base] and k[0] == k[1] and k[4] in (2, 4, 8, 16)
+            same_edge = [c for c in cfgs if c[0] == c[1] == k[0]]
+            assert k[3] == max(c[3] for c in same_edge)
+            assert k[2] == min(c[2] for c in same_edge if c[3] == k[3])
+            assert all(h.config_compiled(v, ta, tb, dtype=dt) for ta, tb in synth.LAYOUTS)
+        with pytest.raises(kt.KtError):
+            h.get_kernel(len(ks), dt)
+    assert {k[:4] for k in h.kernels()[164:]} == {(16, 16, 1, 64), (32, 32, 1, 64),
+                                                  (64, 64, 2, 64), (128, 128, 4, 64)}
+    v8 = next(v for v, k in enumerate(h.kernels()) if k[4] == 8)
+    assert h.kernel_workspace_bytes(100, 50, 1000, 2, id=v8) == 8 * 2 * 100 * 50 * 4
+    assert h.kernel_workspace_bytes(100, 50, 129, 2, id=v8) == -(-3 * 2 * 100 * 50 * 4 // 256) * 256
+    assert h.kernel_workspace_bytes(4096, 4096, 8192, 1, id=v8) == 0
+    with pytest.raises(kt.KtError):
+        h.kernel_workspace_bytes(8, 8, 8, id=len(h.kernels()))
 
 
 def test_sweep_workspace_query(kt):
@@ -144,3 +177,22 @@ def test_conv_queries(kt):
     h = kt.Handle(-1)
     with pytest.raises(kt.KtError):
         h.conv2d(kt.CONV_IM2COL, kt.conv_shape(1, 8, 8, 4, 4), 8, 8, None, False, 8, 8, 1 << 20)
+
+
+def test_pipeline_query(kt):
+    """Which BF16 / FP8 pipeline a call takes (host only): LDS DMA when every
+    row starts on a 16-byte boundary and the contiguous extents are whole
+    16-byte chunks."""
+    BF16, FP8 = kt.BF16, kt.FP8E4M3
+    shp = kt.shape(64, 64, 64)
+    assert kt.Handle.lp_pipeline_dma(BF16, shp, 0x1000, 64, 0, 0x2000, 64, 0)
+    assert not kt.Handle.lp_pipeline_dma(0, shp, 0x1000, 64, 0, 0x2000, 64, 0)          # FP32
+    assert not kt.Handle.lp_pipeline_dma(BF16, shp, 0x1008, 64, 0, 0x2000, 64, 0)       # base
+    assert not kt.Handle.lp_pipeline_dma(BF16, shp, 0x1000, 68, 0, 0x2000, 64, 0)       # lda
+    assert not kt.Handle.lp_pipeline_dma(BF16, kt.shape(64, 64, 60), 0x1000, 64, 0, 0x2000, 64, 0)
+    assert not kt.Handle.lp_pipeline_dma(BF16, kt.shape(64, 60, 64), 0x1000, 64, 0, 0x2000, 64, 0)
+    assert kt.Handle.lp_pipeline_dma(BF16, kt.shape(60, 64, 64, 1, 0, 1), 0x1000, 64, 0, 0x2000,
+                                     64, 0)                                             # M free
+    assert not kt.Handle.lp_pipeline_dma(FP8, shp, 0x1000, 72, 0, 0x2000, 64, 0)
+    assert not kt.Handle.lp_pipeline_dma(BF16, kt.shape(64, 64, 64, 2), 0x1000, 64, 4100, 0x2000,
+                                         64, 4096)                                      # stride

@@ -282,7 +282,7 @@ def test_exhaustive_selector_times_every_config_once_and_caches(gpu):
         h.fit_selector(kt.SEL_EXHAUSTIVE, [], np.zeros((0, 0), np.int64), [])
         s = (1024, 768, 512, 4, 1, 0)
         cid = h.select(*s)
-        assert 0 <= cid < h.num_configs()
+        assert 0 <= cid < h.num_kernels()
         assert h.select(*s) == cid
         ws_bytes = kt.Handle.sweep_workspace_bytes([s])
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
@@ -306,7 +306,7 @@ def test_exhaustive_selector_times_every_config_once_and_caches(gpu):
         assert np.all(np.abs(C[:, :, cols] - ref_c) <= tol)
         h.fit_selector(kt.SEL_EXHAUSTIVE, [], np.zeros((0, 0), np.int64), [], dtype=kt.BF16)
         cb = h.select(*s, dtype=kt.BF16)
-        assert 0 <= cb < h.num_configs(kt.BF16)
+        assert 0 <= cb < h.num_kernels(kt.BF16)
         d_shapes = torch.zeros((1, 5), dtype=torch.int64, device="cuda")
         d_ids = torch.zeros(1, dtype=torch.int32, device="cuda")
         with pytest.raises(kt.KtError) as e:
