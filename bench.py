@@ -243,12 +243,18 @@ VGG16_FC = [(7 * 7 * 512, 4096), (4096, 4096), (4096, 1000)]
 def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
     """Single-image VGG16 inference (224x224x3, random weights scaled by
     1/sqrt(fan-in), FP32, NHWC): 13 3x3 convolutions with ReLU, 5 max pools,
-    3 fully connected layers run as 1x1 convolutions of a 1x1 image.  Per
-    layer: the deployed selector's configuration (config -1) with im2col,
-    with im2col and automatic split-K, and with Winograd F(2x2,3x3) for the
-    3x3 layers; and every configuration of each lowering (plus split counts
-    2..32 for the M = 1 fully connected layers) for the exhaustive best.  The
-    inference is then timed end to end with each per-layer choice."""
+    3 fully connected layers run as 1x1 convolutions of a 1x1 image.
+
+    The selector's inference takes no timing: a fixed lowering rule (Winograd
+    with filters transformed at load for the 3x3 stride-1 layers, im2col for
+    the rest) and the deployed selector's kernel for every GEMM (config -1;
+    a selected split-K kernel runs split -- the fully connected layers, M = 1,
+    lie outside the training shapes and go to the fallback, which times the
+    chosen kernels and their split-K variants once).  The exhaustive
+    reference takes, per layer, the fastest of every lowering x every
+    configuration (x split counts 2..32 for the fully connected layers).
+    Also reported: the best lowering per layer among the selector's options
+    chosen by timing them (labelled as such)."""
     layers = []   # (kind, conv_shape)
     H, C = 224, 3
     for v in VGG16_CONV:
@@ -320,7 +326,7 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
         return e0.elapsed_time(e1) / n
 
     cfgs = h.configs()
-    per, sel_choice, ex_choice = [], [], []
+    per, sel_choice, ex_choice, rule_choice = [], [], [], []
     for li, cs in enumerate(convs):
         xin = torch.empty(cs.H * cs.W * cs.Cin, dtype=torch.float32, device="cuda")
         h.fill_uniform(xin, xin.numel(), synth.operand_seed(synth.SEED + 200 + li, 0), stream=stream)
@@ -358,32 +364,46 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
                 row["winograd_pretransformed"] = {"ms_selected": round(t_pre, 4)}
         sel_choice.append(min(sel_opts)[1])
         ex_choice.append(min(ex_opts)[1])
+        # the selector's pick for this layer's GEMM under the lowering rule
+        algo_r = kt.CONV_WINOGRAD_PRETRANSFORMED if (cs.R == 3 and cs.stride == 1) else kt.CONV_IM2COL
+        g_shape = kt.Handle.conv_gemm_shape(cs, kt.CONV_WINOGRAD if algo_r != kt.CONV_IM2COL else algo_r)
+        pick = h.select(*g_shape)
+        row["rule"] = {"lowering": "winograd_pretransformed" if algo_r != kt.CONV_IM2COL else "im2col",
+                       "selected_kernel": list(h.get_kernel(pick)[0]),
+                       "ms": round(timed(lambda: h.conv2d(algo_r, cs, xin, wt_of(li, algo_r), biases[li],
+                                                          True, out, ws, ws_bytes, stream=stream),
+                                         reps), 4)}
+        rule_choice.append((algo_r, -1, 1))
         per.append(row)
     ms = {
-        "im2col_selected": timed(lambda: forward([(kt.CONV_IM2COL, -1, 1)] * len(convs)), reps),
-        "winograd_selected": timed(lambda: forward([(kt.CONV_WINOGRAD if cs.R == 3 else kt.CONV_IM2COL,
+        "selector": timed(lambda: forward(rule_choice), reps),
+        "exhaustive": timed(lambda: forward(ex_choice), reps),
+        "im2col_selector": timed(lambda: forward([(kt.CONV_IM2COL, -1, 1)] * len(convs)), reps),
+        "winograd_selector": timed(lambda: forward([(kt.CONV_WINOGRAD if cs.R == 3 else kt.CONV_IM2COL,
                                                      -1, 1) for cs in convs]), reps),
-        "best_lowering_selected": timed(lambda: forward(sel_choice), reps),
-        "best_lowering_exhaustive": timed(lambda: forward(ex_choice), reps),
+        "timed_lowering_selector_kernels": timed(lambda: forward(sel_choice), reps),
     }
-    # the selected inference captured once in a graph and replayed
-    out_eager = forward(sel_choice).clone()
+    # the selector's inference captured once in a graph and replayed
+    out_eager = forward(rule_choice).clone()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        out_buf = forward(sel_choice, torch.cuda.current_stream())
+        out_buf = forward(rule_choice, torch.cuda.current_stream())
     g.replay()
     torch.cuda.synchronize()
     graph_ok = bool(torch.equal(out_buf, out_eager))
-    ms["best_lowering_selected_graph"] = timed(g.replay, reps)
+    ms["selector_graph"] = timed(g.replay, reps)
     torch.cuda.synchronize()
     names = {kt.CONV_IM2COL: "im2col", kt.CONV_WINOGRAD: "winograd",
              kt.CONV_WINOGRAD_PRETRANSFORMED: "winograd_pretransformed"}
+    fc = [r for r in per if r["H"] == 1]
     return {"ms_per_inference": {kk: round(v, 4) for kk, v in ms.items()},
             "gflop_direct": round(flops / 1e9, 2),
-            "tflops_effective_best_lowering_selected": round(flops / (ms["best_lowering_selected"] * 1e-3) / 1e12, 2),
-            "selected_pct_of_exhaustive": round(100 * ms["best_lowering_exhaustive"] / ms["best_lowering_selected"], 2),
-            "selected_choice": [[names[a], sp] for a, _, sp in sel_choice],
+            "tflops_effective_selector": round(flops / (ms["selector"] * 1e-3) / 1e12, 2),
+            "selector_pct_of_exhaustive": round(100 * ms["exhaustive"] / ms["selector"], 2),
+            "fc1_selector_vs_exhaustive": round(fc[0]["rule"]["ms"] / fc[0]["im2col"]["ms_exhaustive"], 3),
+            "exhaustive_choice": [[names[a], list(cfgs[c]), sp] for a, c, sp in ex_choice],
+            "timed_lowering_choice": [[names[a], sp] for a, _, sp in sel_choice],
             "graph_replay_matches_eager": graph_ok,
             "layers": per}
 
@@ -449,20 +469,21 @@ def deploy_info(chosen, n_configs):
     return out
 
 
-def grouped_section(kt, h, torch, synth, stream, reps=20):
-    """The persistent grouped BF16 GEMM on its workload (512 uneven GEMMs,
-    M, N, K log-uniform in 32..2048, A M x K, B K x N, FP32 out): the
-    library's autotuner picks (tile, schedule, order, work-groups per CU) on
-    the real group, then one hipGraph launch runs every member.  Reported
-    against the sum over members of each one's roofline time at peak BF16
-    MFMA rate and HBM bandwidth, and against one kt_gemm launch per member."""
-    shapes = synth.grouped_shapes()
+def _grouped_layout(kt, h, torch, synth, shapes, stream, padded):
+    """Device operands of the grouped workload: BF16 A (M x lda) and B
+    (K x ldb) converted on the GPU from one seeded FP32 stream, FP32 C.
+    padded: rows padded to a multiple of 8 elements (16 bytes, allocated in
+    full); else dense rows.  Returns pointers, leading dimensions and the FP32
+    source of each member's values (for the error report)."""
     a256 = lambda v: (v + 255) // 256 * 256
-    offs_a, offs_b, offs_c = [], [], []
+    rnd = (lambda v: (v + 7) // 8 * 8) if padded else (lambda v: v)
+    offs_a, offs_b, offs_c, ld = [], [], [], []
     na = nb = nc = 0
     for (M, N, K) in shapes:
-        offs_a.append(na); na += a256(M * K * 2)
-        offs_b.append(nb); nb += a256(K * N * 2)
+        lda, ldb = rnd(K), rnd(N)
+        ld.append((lda, ldb, N))
+        offs_a.append(na); na += a256(M * lda * 2)
+        offs_b.append(nb); nb += a256(K * ldb * 2)
         offs_c.append(nc); nc += a256(M * N * 4)
     src = torch.empty((max(na, nb) + 3) // 2, dtype=torch.float32, device="cuda")
     h.fill_uniform(src, src.numel(), synth.operand_seed(synth.SEED + 4, 0), stream=stream)
@@ -471,76 +492,102 @@ def grouped_section(kt, h, torch, synth, stream, reps=20):
     pc = torch.empty(nc, dtype=torch.uint8, device="cuda")
     h.convert_bf16(src, na // 2, pa, stream=stream)
     h.convert_bf16(src, nb // 2, pb, stream=stream)
-    A = [pa.data_ptr() + o for o in offs_a]
-    B = [pb.data_ptr() + o for o in offs_b]
-    C = [pc.data_ptr() + o for o in offs_c]
-    wsb = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
-    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    best, best_ms, evals = h.autotune_grouped(shapes, A, B, C, ws, wsb, stream=stream)
-    tune_s = time.perf_counter() - t0
-    plan = h.grouped_plan(shapes, A, B, C, workspace=ws, ws_bytes=wsb, stream=stream)
-    for _ in range(3):
-        h.grouped_launch(plan, stream=stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        h.grouped_launch(plan, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    e0.record(stream)
-    for i, (M, N, K) in enumerate(shapes):
-        h.gemm_raw(kt.BF16, kt.shape(M, N, K), 1.0, A[i], K, 0, B[i], N, 0, 0.0, C[i], N, 0,
-                   config_id=best[0], stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    sep_ms = e0.elapsed_time(e1)
-    # one launch per member with the configuration the BF16 selector picks
-    # for it (when one is fitted), each member's selection made beforehand
-    sel_ms = None
-    if h.selector_info(kt.BF16)["kind"] >= 0:
-        picks = [h.select(M, N, K, dtype=kt.BF16) for (M, N, K) in shapes]
+    return dict(A=[pa.data_ptr() + o for o in offs_a], B=[pb.data_ptr() + o for o in offs_b],
+                C=[pc.data_ptr() + o for o in offs_c], ld=ld, src=src, offs_a=offs_a,
+                offs_b=offs_b, offs_c=offs_c, bufs=(pa, pb, pc))
 
-        def run_selected():
-            for i, (M, N, K) in enumerate(shapes):
-                h.gemm_raw(kt.BF16, kt.shape(M, N, K), 1.0, A[i], K, 0, B[i], N, 0, 0.0, C[i], N, 0,
-                           config_id=picks[i], stream=stream)
-        run_selected()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(3):
-            run_selected()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        sel_ms = e0.elapsed_time(e1) / 3
+
+def grouped_section(kt, h, torch, synth, stream, reps=20):
+    """The persistent grouped BF16 GEMM on its workload (512 uneven GEMMs,
+    M, N, K log-uniform in 32..2048, A M x K, B K x N, FP32 out): the
+    library's autotuner picks (tile pair, small-member area, schedule, order,
+    work-groups per CU) on the real group, then one hipGraph launch runs every
+    member.  Two storage layouts: rows padded to 16 bytes (the DMA pipeline)
+    and dense rows.  Reported against the sum over members of each one's
+    roofline time at peak BF16 MFMA rate and HBM bandwidth, and against one
+    kt_gemm launch per member with the configuration the BF16 selector picks
+    for it (the same storage, whole rows promised)."""
+    shapes = synth.grouped_shapes()
     flops = sum(2.0 * m * n * k for (m, n, k) in shapes)
     roof_ms = sum(max(2.0 * m * n * k / 2.5e15, (2.0 * (m * k + k * n) + 4.0 * m * n) / 8e12)
                   for (m, n, k) in shapes) * 1e3
-    # per-member relative Frobenius error of the graph launch's output
-    # against the product of the original FP32 operands in FP64 (computed on
-    # the GPU here; the parity tests hold each member to 1e-2 against the
-    # CPU oracle)
-    h.grouped_launch(plan, stream=stream)
-    torch.cuda.synchronize()
-    errs = []
-    for i, (M, N, K) in enumerate(shapes):
-        a64 = src[offs_a[i] // 2: offs_a[i] // 2 + M * K].view(M, K).double()
-        b64 = src[offs_b[i] // 2: offs_b[i] // 2 + K * N].view(K, N).double()
-        ref = a64 @ b64
-        c = pc[offs_c[i]: offs_c[i] + M * N * 4].view(torch.float32).view(M, N).double()
-        errs.append(float(torch.linalg.norm(c - ref) / torch.linalg.norm(ref)))
-    errs = np.array(errs)
-    del src
-    h.grouped_destroy(plan)
-    return {"members": len(shapes), "gflop": round(flops / 1e9, 2),
-            "config": list(h.get_config(best[0], kt.BF16)), "schedule": best[1], "order": best[2],
-            "wgs_per_cu": best[3], "autotune_evaluations": evals, "autotune_s": round(tune_s, 3),
+    wsb = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    out = {"members": len(shapes), "gflop": round(flops / 1e9, 2),
+           "sum_member_roofline_ms": round(roof_ms, 4)}
+    for name, padded in (("rows_padded_16B", True), ("dense_rows", False)):
+        L = _grouped_layout(kt, h, torch, synth, shapes, stream, padded)
+        A, B, C, ld = L["A"], L["B"], L["C"], L["ld"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        best, best_ms, evals = h.autotune_grouped(shapes, A, B, C, ws, wsb, stream=stream, ld=ld)
+        tune_s = time.perf_counter() - t0
+        plan = h.grouped_plan(shapes, A, B, C, workspace=ws, ws_bytes=wsb, stream=stream, ld=ld)
+        n_work = h.grouped_info(plan)[0]
+        for _ in range(3):
+            h.grouped_launch(plan, stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            h.grouped_launch(plan, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        # one launch per member: the selector's pick (when a BF16 selector is
+        # fitted) and the grouped plan's large tile
+        h.set_full_rows(padded)
+        sel_ms = None
+        if h.selector_info(kt.BF16)["kind"] >= 0:
+            picks = [h.select(M, N, K, dtype=kt.BF16) for (M, N, K) in shapes]
+
+            def run_selected():
+                for i, (M, N, K) in enumerate(shapes):
+                    h.gemm_raw(kt.BF16, kt.shape(M, N, K), 1.0, A[i], ld[i][0], 0, B[i], ld[i][1], 0,
+                               0.0, C[i], N, 0, config_id=picks[i], stream=stream)
+            run_selected()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(3):
+                run_selected()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sel_ms = e0.elapsed_time(e1) / 3
+        e0.record(stream)
+        for i, (M, N, K) in enumerate(shapes):
+            h.gemm_raw(kt.BF16, kt.shape(M, N, K), 1.0, A[i], ld[i][0], 0, B[i], ld[i][1], 0, 0.0,
+                       C[i], N, 0, config_id=best[0], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        same_ms = e0.elapsed_time(e1)
+        h.set_full_rows(False)
+        # per-member relative Frobenius error of the graph launch's output
+        # against the product of the original FP32 operands in FP64 (computed
+        # on the GPU here; the parity tests hold each member to 1e-2 against
+        # the CPU oracle)
+        h.grouped_launch(plan, stream=stream)
+        torch.cuda.synchronize()
+        errs = []
+        src, pc = L["src"], L["bufs"][2]
+        for i, (M, N, K) in enumerate(shapes):
+            lda, ldb, _ = ld[i]
+            oa, ob = L["offs_a"][i] // 2, L["offs_b"][i] // 2
+            a64 = src[oa: oa + M * lda].view(M, lda)[:, :K].double()
+            b64 = src[ob: ob + K * ldb].view(K, ldb)[:, :N].double()
+            ref = a64 @ b64
+            c = pc[L["offs_c"][i]: L["offs_c"][i] + M * N * 4].view(torch.float32).view(M, N).double()
+            errs.append(float(torch.linalg.norm(c - ref) / torch.linalg.norm(ref)))
+        errs = np.array(errs)
+        h.grouped_destroy(plan)
+        bm, bn, tt, bk = h.get_config(best[0], kt.BF16)
+        out[name] = {
+            "tile": [bm, bn, tt, bk],
+            "small_tile": list(h.get_config(best[1], kt.BF16)) if best[1] >= 0 else None,
+            "small_max_area": best[2], "schedule": best[3], "order": best[4],
+            "wgs_per_cu": best[5], "work_items": n_work,
+            "autotune_evaluations": evals, "autotune_s": round(tune_s, 3),
             "ms_per_launch": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
-            "sum_member_roofline_ms": round(roof_ms, 4), "frac_of_sum_roofline": round(roof_ms / ms, 4),
             "roofline": {"bound": "per-member max(MFMA at 2.5 PF/s, HBM at 8 TB/s), summed",
                          "achieved_ms": round(ms, 4), "roofline_ms": round(roof_ms, 4),
                          "frac": round(roof_ms / ms, 4)},
@@ -550,8 +597,10 @@ def grouped_section(kt, h, torch, synth, stream, reps=20):
                 "members_within_bound": int((errs <= 1e-2).sum())},
             "separate_launches_selected_ms": None if sel_ms is None else round(sel_ms, 3),
             "speedup_vs_separate_selected": None if sel_ms is None else round(sel_ms / ms, 2),
-            "separate_launches_same_tile_ms": round(sep_ms, 3),
-            "speedup_vs_separate_same_tile": round(sep_ms / ms, 2)}
+            "separate_launches_same_tile_ms": round(same_ms, 3),
+            "speedup_vs_separate_same_tile": round(same_ms / ms, 2)}
+        del L
+    return out
 
 
 def selection_latency(kt, h, torch, problems, stream, reps=20):
@@ -1090,7 +1139,7 @@ def main(argv=None):
     _log(f"bench: split-K {json.dumps(out['split_k'])}")
     out["vgg16"] = vgg16_section(kt, h, torch, synth, stream)
     _log(f"bench: VGG16 {json.dumps(out['vgg16']['ms_per_inference'])}, "
-         f"{out['vgg16']['selected_pct_of_exhaustive']} % of exhaustive")
+         f"{out['vgg16']['selector_pct_of_exhaustive']} % of exhaustive")
     _log(f"bench: single GEMM {json.dumps(out['single_gemm_256'])}; repeatability "
          f"{json.dumps(out['repeatability'])}")
     if not a.no_lowp:

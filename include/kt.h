@@ -179,14 +179,22 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
 
 /* Which pipeline the BF16 / FP8 kernels take for these operands (host only,
  * nothing launched): *dma = 1 when every row of A and B starts on a 16-byte
- * boundary (base, leading dimension and, for batch > 1, batch stride) and
- * each operand's contiguous extent (K for an operand stored K-contiguous,
- * M or N otherwise) is a whole number of 16-byte chunks -- tiles then move
+ * boundary (base, leading dimension and, for batch > 1, batch stride) and no
+ * 16-byte chunk read leaves an operand: its contiguous extent (K for an
+ * operand stored K-contiguous, M or N otherwise) is a whole number of 16-byte
+ * chunks or, after kt_set_full_rows(h, 1), at least one chunk with the
+ * leading dimension reaching the next 16-byte boundary -- tiles then move
  * from HBM to LDS by LDS DMA with several stages in flight; otherwise 0
  * (register-staged loads; same results).  Always 0 for KT_F32. */
-kt_status kt_lp_pipeline(kt_dtype dtype, const kt_shape* s, const void* A, int64_t lda,
-                         int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+kt_status kt_lp_pipeline(kt_handle h, kt_dtype dtype, const kt_shape* s, const void* A,
+                         int64_t lda, int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
                          int32_t* dma);
+/* Promise (enabled = 1) that every BF16 / FP8 operand later passed to this
+ * handle's GEMM calls is allocated to whole rows of its leading dimension,
+ * the last row included, so that the DMA pipeline may read a row up to its
+ * next 16-byte boundary beyond the logical extent (values there only reach
+ * outputs that are not stored, or are zeroed in LDS).  Default 0. */
+kt_status kt_set_full_rows(kt_handle h, int32_t enabled);
 
 /* Split-K form of kt_gemm for deep products with few output tiles, the
  * tall-skinny / very deep K case that section 3 names as its kernel's worst
@@ -284,8 +292,10 @@ kt_status kt_conv2d_workspace_bytes(const kt_conv_shape* c, kt_conv_algo algo, i
 /* y = conv(x, w) + bias, then ReLU when relu != 0.  x, w, bias (NULL = no
  * bias; Cout floats), y and workspace are device pointers; y must not alias
  * x or the workspace.  config_id: FP32 configuration of the GEMM, -1 = the
- * configuration of the kernel the fitted selector picks for
- * kt_conv2d_gemm_shape (the layer's split is `splits`).  splits (im2col only; Winograd
+ * kernel the fitted selector picks for kt_conv2d_gemm_shape (with splits = 1
+ * and im2col, a selected split-K kernel runs split with the partial planes in
+ * the kt_set_workspace buffer when they fit; otherwise its configuration
+ * runs with the layer's `splits`).  splits (im2col only; Winograd
  * takes 0 or 1 and never splits): 1 = the plain GEMM, otherwise the GEMM
  * runs as kt_gemm_splitk with this splits value (0 = automatic), which suits
  * the fully connected layers of a single image (M = 1, deep K).  Empty n, Ho
@@ -619,31 +629,41 @@ kt_status kt_load(kt_handle h, const char* path);
  * major M x K, BF16 B_i row-major K x N, FP32 C_i row-major M x N; members
  * must have batch 1 and no transposes) run by one persistent kernel: the
  * members' output tiles form one work list that resident work-groups walk.
- * The kernel is captured with its setup in a hipGraph; one plan = one graph
- * launch per run. */
+ * Members with M * N <= small_max_area take the smaller of the plan's two
+ * tiles.  The kernel is captured with its setup in a hipGraph; one plan = one
+ * graph launch per run.  Member leading dimensions: `ld` is a host array of
+ * 3n values (lda_i >= K, ldb_i >= N, ldc_i >= N), or NULL for dense rows.  A
+ * member whose A and B rows start on 16-byte boundaries (16-byte aligned
+ * pointer, leading dimension a multiple of 8) and whose last 16-byte chunk of
+ * a row ends within the leading dimension moves tiles by LDS DMA; its rows
+ * are then read up to the next 16-byte boundary, so every row (the last one
+ * included) must be allocated to its full leading dimension. */
 typedef struct {
-  int32_t config_id;     /* BF16 tile configuration (kt_get_config(KT_BF16, id)) */
-  int32_t schedule;      /* 0: static round robin over work-groups; 1: atomic work counter */
-  int32_t order;         /* 0: members in the given order; 1: largest K first */
-  int32_t wgs_per_cu;    /* persistent work-groups per compute unit (1..4) */
-  uint32_t* visits;      /* optional device counters [n_work]: each work item adds 1 (tests) */
+  int32_t config_id;        /* BF16 tile of the members (kt_get_config(KT_BF16, id)) */
+  int32_t small_config_id;  /* BF16 tile of members with M * N <= small_max_area; -1 = none */
+  int64_t small_max_area;
+  int32_t schedule;         /* 0: static round robin over work-groups; 1: atomic work counter */
+  int32_t order;            /* 0: members in the given order; 1: largest K first */
+  int32_t wgs_per_cu;       /* persistent work-groups per compute unit (1..4) */
+  uint32_t* visits;         /* optional device counters [n_work]: each work item adds 1 (tests) */
 } kt_grouped_opts;
 
 typedef struct kt_grouped_plan_s* kt_grouped_plan;
 
 /* Device workspace for a group (descriptors, work list, counter). */
 kt_status kt_grouped_workspace_bytes(const kt_shape* shapes, int32_t n, size_t* bytes);
-/* Number of tile configurations the grouped kernel is compiled for. */
+/* Number of tile pairs (large, small) the grouped kernel is compiled for. */
 kt_status kt_grouped_num_candidates(int32_t* n);
 /* Build a plan: uploads descriptors and the work list into the workspace
  * (which must stay untouched while the plan lives) and captures the graph.
  * A, B, C are host arrays of n device pointers.  opts NULL = the options the
- * autotuner found on this handle, else a default.  Synchronizes `stream`. */
+ * autotuner found on this handle, else a default.  KT_EUNSUPPORTED for a
+ * tile pair that is not compiled.  Synchronizes `stream`. */
 kt_status kt_grouped_plan_create(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
                                  const void* const* A, const void* const* B, float* const* C,
-                                 float alpha, float beta, const kt_grouped_opts* opts,
-                                 void* workspace, size_t ws_bytes, void* stream,
-                                 kt_grouped_plan* out);
+                                 const int64_t* ld, float alpha, float beta,
+                                 const kt_grouped_opts* opts, void* workspace, size_t ws_bytes,
+                                 void* stream, kt_grouped_plan* out);
 /* One graph launch of the plan on `stream` (asynchronous). */
 kt_status kt_grouped_plan_launch(kt_handle h, kt_grouped_plan plan, void* stream);
 /* Work-list length and options of a plan. */
@@ -651,16 +671,17 @@ kt_status kt_grouped_plan_info(kt_grouped_plan plan, int32_t* n_work, kt_grouped
 kt_status kt_grouped_plan_destroy(kt_grouped_plan plan);
 /* Plan, launch once, synchronize, destroy. */
 kt_status kt_grouped_gemm(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
-                          const void* const* A, const void* const* B, float* const* C, float alpha,
-                          float beta, const kt_grouped_opts* opts, void* workspace, size_t ws_bytes,
-                          void* stream);
-/* The library's autotuner: successive halving over (tile configuration,
- * schedule, order, work-groups per CU), timing whole graph launches of the
- * real group (C is overwritten with alpha = 1, beta = 0).  The winner is
- * returned and kept on the handle as the default for later plans. */
+                          const void* const* A, const void* const* B, float* const* C,
+                          const int64_t* ld, float alpha, float beta, const kt_grouped_opts* opts,
+                          void* workspace, size_t ws_bytes, void* stream);
+/* The library's autotuner: successive halving over (tile pair, small-member
+ * area in {0, 128^2, 256^2, 512^2}, schedule, order, work-groups per CU),
+ * timing whole graph launches of the real group (C is overwritten with
+ * alpha = 1, beta = 0).  The winner is returned and kept on the handle as the
+ * default for later plans. */
 kt_status kt_autotune_grouped(kt_handle h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
                               const void* const* A, const void* const* B, float* const* C,
-                              void* workspace, size_t ws_bytes, void* stream,
+                              const int64_t* ld, void* workspace, size_t ws_bytes, void* stream,
                               kt_grouped_opts* best, float* best_ms, int32_t* evaluations);
 
 /* ------------------------------------------------------- MLP cost model */

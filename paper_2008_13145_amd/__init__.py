@@ -57,8 +57,8 @@ class Eval(ctypes.Structure):
 
 
 class GroupedOpts(ctypes.Structure):
-    _fields_ = [("config_id", c_i32), ("schedule", c_i32), ("order", c_i32), ("wgs_per_cu", c_i32),
-                ("visits", c_vp)]
+    _fields_ = [("config_id", c_i32), ("small_config_id", c_i32), ("small_max_area", c_i64),
+                ("schedule", c_i32), ("order", c_i32), ("wgs_per_cu", c_i32), ("visits", c_vp)]
 
 
 class ConvShape(ctypes.Structure):
@@ -114,8 +114,9 @@ _SIGS = {
     "kt_kernel_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32,
                                           ctypes.POINTER(c_sz)]),
     "kt_set_workspace": (c_i32, [c_vp, c_vp, c_sz]),
-    "kt_lp_pipeline": (c_i32, [c_i32, ctypes.POINTER(Shape), c_vp, c_i64, c_i64, c_vp, c_i64, c_i64,
-                               ctypes.POINTER(c_i32)]),
+    "kt_lp_pipeline": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i64, c_i64, c_vp, c_i64,
+                               c_i64, ctypes.POINTER(c_i32)]),
+    "kt_set_full_rows": (c_i32, [c_vp, c_i32]),
     "kt_sweep_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_sweep": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_i32,
                          ctypes.POINTER(SweepOpts), c_vp, c_sz, c_vp, c_vp]),
@@ -154,16 +155,16 @@ _SIGS = {
     "kt_grouped_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, ctypes.POINTER(c_sz)]),
     "kt_grouped_num_candidates": (c_i32, [ctypes.POINTER(c_i32)]),
     "kt_grouped_plan_create": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp,
-                                       c_f32, c_f32, ctypes.POINTER(GroupedOpts), c_vp, c_sz, c_vp,
-                                       ctypes.POINTER(c_vp)]),
+                                       c_vp, c_f32, c_f32, ctypes.POINTER(GroupedOpts), c_vp, c_sz,
+                                       c_vp, ctypes.POINTER(c_vp)]),
     "kt_grouped_plan_launch": (c_i32, [c_vp, c_vp, c_vp]),
     "kt_grouped_plan_info": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(GroupedOpts)]),
     "kt_grouped_plan_destroy": (c_i32, [c_vp]),
-    "kt_grouped_gemm": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp, c_f32,
-                                c_f32, ctypes.POINTER(GroupedOpts), c_vp, c_sz, c_vp]),
+    "kt_grouped_gemm": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp, c_vp,
+                                c_f32, c_f32, ctypes.POINTER(GroupedOpts), c_vp, c_sz, c_vp]),
     "kt_autotune_grouped": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32, c_vp, c_vp, c_vp, c_vp,
-                                    c_sz, c_vp, ctypes.POINTER(GroupedOpts), ctypes.POINTER(c_f32),
-                                    ctypes.POINTER(c_i32)]),
+                                    c_vp, c_sz, c_vp, ctypes.POINTER(GroupedOpts),
+                                    ctypes.POINTER(c_f32), ctypes.POINTER(c_i32)]),
     "kt_mlp_workspace_bytes": (c_i32, [c_i32, c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "kt_mlp_num_params": (c_i32, [c_i32, ctypes.POINTER(c_i32)]),
     "kt_mlp_features": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
@@ -299,15 +300,16 @@ class Handle:
                                                      int(id), ctypes.byref(b)))
         return b.value
 
-    @staticmethod
-    def lp_pipeline_dma(dtype, shp: Shape, A, lda, sA, B, ldb, sB) -> bool:
+    def lp_pipeline_dma(self, dtype, shp: Shape, A, lda, sA, B, ldb, sB) -> bool:
         """True when BF16 / FP8 kernels run these operands through the LDS DMA pipeline."""
         v = c_i32()
-        st = lib().kt_lp_pipeline(int(dtype), ctypes.byref(shp), _ptr(A), int(lda), int(sA), _ptr(B),
-                                  int(ldb), int(sB), ctypes.byref(v))
-        if st != 0:
-            raise KtError(st, "pipeline query")
+        self._check(self.L.kt_lp_pipeline(self.h, int(dtype), ctypes.byref(shp), _ptr(A), int(lda),
+                                          int(sA), _ptr(B), int(ldb), int(sB), ctypes.byref(v)))
         return bool(v.value)
+
+    def set_full_rows(self, enabled: bool):
+        """Promise that operands are allocated to whole rows of their leading dimension."""
+        self._check(self.L.kt_set_full_rows(self.h, 1 if enabled else 0))
 
     def set_workspace(self, ws, ws_bytes=None):
         """Device buffer (tensor or pointer) kt_gemm gives split-K kernels; None clears it."""
@@ -782,18 +784,35 @@ class Handle:
             arr[i] = _ptr(p)
         return arr
 
+    @staticmethod
+    def _ld_array(ld, n):
+        """Member leading dimensions: None (dense) or a list of (lda, ldb, ldc)."""
+        if ld is None:
+            return None
+        a = np.ascontiguousarray(np.asarray(ld, dtype=np.int64).reshape(n, 3))
+        return a
+
+    @staticmethod
+    def _opts_tuple(o):
+        return (o.config_id, o.small_config_id, int(o.small_max_area), o.schedule, o.order,
+                o.wgs_per_cu)
+
     def grouped_plan(self, shapes, A, B, C, alpha=1.0, beta=0.0, opts=None, workspace=None,
-                     ws_bytes=0, dtype=BF16, stream=None):
-        """shapes: list of (M, N, K); A, B, C: lists of device buffers."""
+                     ws_bytes=0, dtype=BF16, stream=None, ld=None):
+        """shapes: list of (M, N, K); A, B, C: lists of device buffers; ld:
+        None or per member (lda, ldb, ldc); opts: GroupedOpts or (config_id,
+        small_config_id, small_max_area, schedule, order, wgs_per_cu[, visits])."""
         arr = shapes_array([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
         plan = c_vp()
         o = None
         if opts is not None:
             o = opts if isinstance(opts, GroupedOpts) else GroupedOpts(*opts)
+        lda = self._ld_array(ld, len(shapes))
         self._check(self.L.kt_grouped_plan_create(
             self.h, dtype, arr, len(shapes), self._ptr_array(A), self._ptr_array(B),
-            self._ptr_array(C), float(alpha), float(beta), None if o is None else ctypes.byref(o),
-            _ptr(workspace), int(ws_bytes), _stream(stream), ctypes.byref(plan)))
+            self._ptr_array(C), None if lda is None else lda.ctypes.data, float(alpha), float(beta),
+            None if o is None else ctypes.byref(o), _ptr(workspace), int(ws_bytes), _stream(stream),
+            ctypes.byref(plan)))
         return plan
 
     def grouped_launch(self, plan, stream=None):
@@ -805,18 +824,20 @@ class Handle:
         st = self.L.kt_grouped_plan_info(plan, ctypes.byref(n), ctypes.byref(o))
         if st != 0:
             raise KtError(st, "plan info")
-        return n.value, (o.config_id, o.schedule, o.order, o.wgs_per_cu)
+        return n.value, self._opts_tuple(o)
 
     def grouped_destroy(self, plan):
         self.L.kt_grouped_plan_destroy(plan)
 
-    def autotune_grouped(self, shapes, A, B, C, workspace, ws_bytes, dtype=BF16, stream=None):
+    def autotune_grouped(self, shapes, A, B, C, workspace, ws_bytes, dtype=BF16, stream=None,
+                         ld=None):
         arr = shapes_array([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
         o = GroupedOpts()
         ms = c_f32()
         ev = c_i32()
+        lda = self._ld_array(ld, len(shapes))
         self._check(self.L.kt_autotune_grouped(
             self.h, dtype, arr, len(shapes), self._ptr_array(A), self._ptr_array(B),
-            self._ptr_array(C), _ptr(workspace), int(ws_bytes), _stream(stream), ctypes.byref(o),
-            ctypes.byref(ms), ctypes.byref(ev)))
-        return (o.config_id, o.schedule, o.order, o.wgs_per_cu), ms.value, ev.value
+            self._ptr_array(C), None if lda is None else lda.ctypes.data, _ptr(workspace),
+            int(ws_bytes), _stream(stream), ctypes.byref(o), ctypes.byref(ms), ctypes.byref(ev)))
+        return self._opts_tuple(o), ms.value, ev.value

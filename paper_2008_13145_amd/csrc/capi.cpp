@@ -87,13 +87,15 @@ static int elem_bytes(int dtype) { return dtype == KT_F32 ? 4 : dtype == KT_BF16
 // which takes the low-precision DMA pipeline.  FP32 rows are always 4-byte
 // aligned (2).
 int32_t operand_alignment(int dtype, const void* p, int64_t ld, int64_t stride, int64_t batch,
-                          int64_t ext) {
+                          int64_t ext, bool full_rows) {
   const int eb = elem_bytes(dtype);
   if ((uintptr_t)p % 4 != 0) return 0;
   if ((ld * eb) % 4 != 0 || (stride * eb) % 4 != 0) return 1;
   const int64_t ce = 16 / eb;
-  if (eb < 4 && (uintptr_t)p % 16 == 0 && ld % ce == 0 && (batch <= 1 || stride % ce == 0) &&
-      ext % ce == 0)
+  // with rows allocated in full, a row's last chunk may end anywhere within
+  // the leading dimension
+  const bool ext_ok = ext % ce == 0 || (full_rows && ext >= ce && ld >= (ext + ce - 1) / ce * ce);
+  if (eb < 4 && (uintptr_t)p % 16 == 0 && ld % ce == 0 && (batch <= 1 || stride % ce == 0) && ext_ok)
     return 3;
   return 2;
 }
@@ -118,8 +120,8 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
   g.lda = lda; g.sA = sA; g.ldb = ldb; g.sB = sB; g.ldc = ldc; g.sC = sC;
   g.alpha = alpha; g.beta = beta;
   g.scaleA = scaleA; g.scaleB = scaleB;
-  g.vecA = operand_alignment(dtype, A, lda, sA, s->batch, s->transA ? s->M : s->K);
-  g.vecB = operand_alignment(dtype, B, ldb, sB, s->batch, s->transB ? s->K : s->N);
+  g.vecA = operand_alignment(dtype, A, lda, sA, s->batch, s->transA ? s->M : s->K, h->full_rows);
+  g.vecB = operand_alignment(dtype, B, ldb, sB, s->batch, s->transB ? s->K : s->N, h->full_rows);
   g.batch = s->batch;
   g.A = A;
   g.B = B;
@@ -298,14 +300,26 @@ kt_status kt_gemm(kt_handle hh, kt_dtype in_dtype, const kt_shape* s, float alph
                     strideC, scaleA, scaleB, id, h->gemm_ws, h->gemm_ws_bytes, (hipStream_t)stream);
 }
 
-kt_status kt_lp_pipeline(kt_dtype dtype, const kt_shape* s, const void* A, int64_t lda,
-                         int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
+kt_status kt_lp_pipeline(kt_handle hh, kt_dtype dtype, const kt_shape* s, const void* A,
+                         int64_t lda, int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
                          int32_t* dma) {
-  if (!s || !dma) return fail(nullptr, KT_EINVAL, "NULL argument");
-  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(nullptr, KT_EINVAL, "bad dtype");
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (!s || !dma) return fail(h, KT_EINVAL, "NULL argument");
+  if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
   *dma = dtype != KT_F32 &&
-         operand_alignment(dtype, A, lda, strideA, s->batch, s->transA ? s->M : s->K) == 3 &&
-         operand_alignment(dtype, B, ldb, strideB, s->batch, s->transB ? s->K : s->N) == 3;
+         operand_alignment(dtype, A, lda, strideA, s->batch, s->transA ? s->M : s->K,
+                           h->full_rows) == 3 &&
+         operand_alignment(dtype, B, ldb, strideB, s->batch, s->transB ? s->K : s->N,
+                           h->full_rows) == 3;
+  return KT_OK;
+}
+
+kt_status kt_set_full_rows(kt_handle hh, int32_t enabled) {
+  Ctx* h = reinterpret_cast<Ctx*>(hh);
+  if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
+  if (enabled != 0 && enabled != 1) return fail(h, KT_EINVAL, "enabled must be 0 or 1");
+  h->full_rows = enabled != 0;
   return KT_OK;
 }
 

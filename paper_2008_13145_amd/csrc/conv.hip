@@ -322,12 +322,23 @@ kt_status kt_conv2d(kt_handle hh, kt_conv_algo algo, const kt_conv_shape* c, con
     bool fused = false;   // bias and activation applied by the split-K reduction
     if (splits == 1) {
       int32_t cfg = config_id;
-      if (cfg < 0) {   // the selected kernel's configuration (the layer's split is `splits`)
-        if ((st = select_config(h, KT_F32, &gs, &cfg)) != KT_OK) return st;
-        cfg = kernel_base(h, KT_F32, cfg);
+      int32_t sel = -1;
+      if (cfg < 0) {
+        if ((st = select_config(h, KT_F32, &gs, &sel)) != KT_OK) return st;
+        cfg = kernel_base(h, KT_F32, sel);
       }
-      st = launch_gemm(h, KT_F32, &gs, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O, 0.f, y,
-                       d.O, gs.M * d.O, nullptr, nullptr, cfg, s);
+      const size_t planes = sel >= 0 ? kernel_plane_bytes(h, KT_F32, &gs, sel) : 0;
+      if (planes > 0 && h->gemm_ws && h->gemm_ws_bytes >= planes) {
+        // a selected split-K kernel runs split, its planes in the handle's
+        // workspace, and its reduction applies the bias and the activation
+        st = splitk_gemm(h, KT_F32, &gs, kernel_slices(h, KT_F32, sel), 1.f, col, gs.K,
+                         gs.M * gs.K, w, d.O, gs.K * d.O, 0.f, y, d.O, gs.M * d.O, nullptr,
+                         nullptr, cfg, h->gemm_ws, h->gemm_ws_bytes, stream, nullptr, bias, relu,
+                         &fused);
+      } else {
+        st = launch_gemm(h, KT_F32, &gs, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O, 0.f, y,
+                         d.O, gs.M * d.O, nullptr, nullptr, cfg, s);
+      }
     } else {
       const size_t main = conv_main_bytes(d, algo);
       st = splitk_gemm(h, KT_F32, &gs, splits, 1.f, col, gs.K, gs.M * gs.K, w, d.O, gs.K * d.O,

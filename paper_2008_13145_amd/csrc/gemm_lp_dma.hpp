@@ -1,8 +1,10 @@
 // Direct-to-LDS pipeline of the low-precision family, taken when every
 // operand row starts on a 16-byte boundary (base, leading dimension and
-// batch stride multiples of 16 bytes) and each operand's contiguous extent
-// (K, or M / N for an operand stored M- / N-contiguous) is whole 16-byte
-// chunks, so that no chunk read crosses the end of a row.  Same configuration knobs and results
+// batch stride multiples of 16 bytes) and no 16-byte chunk read can leave
+// the operand: its contiguous extent (K, or M / N for an operand stored M- /
+// N-contiguous) is whole chunks, or (grouped members, whose rows are
+// allocated to the full leading dimension) the last chunk of a row ends
+// within the leading dimension.  Same configuration knobs and results
 // contract as gemm_lp.hpp; what changes is how tiles reach the MFMAs:
 //
 // * Global -> LDS with gfx950's 16-byte LDS DMA (global_load_lds_dwordx4):
@@ -126,7 +128,7 @@ __device__ __forceinline__ void lp_dma_issue(const GemmArgs& args, const char* _
       int64_t row = c0 + r;
       row = row < lim ? row : lim - 1;
       int64_t kk = k0 + (int64_t)c * CE;
-      kk = kk < args.K ? kk : args.K - CE;  // chunks beyond K (K is whole chunks): the last one
+      kk = kk < args.K ? kk : ((args.K - 1) / CE) * CE;   // chunks beyond K: the last one
       elem = row * ld + kk;
     } else {
       const int ROWB = rows_c * EB, CPR = ROWB / 16;
@@ -137,7 +139,7 @@ __device__ __forceinline__ void lp_dma_issue(const GemmArgs& args, const char* _
       int64_t kr = k0 + k;
       kr = kr < args.K ? kr : args.K - 1;
       int64_t col = c0 + (int64_t)c * CE;
-      col = col < lim ? col : lim - CE;     // the extent is whole chunks
+      col = col < lim ? col : ((lim - 1) / CE) * CE;      // chunks beyond the extent: the last
       elem = kr * ld + col;
     }
     char* dst = stage + (isA ? 0 : Cfg::A_BYTES) + blk * 1024;

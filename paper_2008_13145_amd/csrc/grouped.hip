@@ -2,19 +2,24 @@
 // a hipGraph, with a tile schedule chosen by the library's own autotuner.
 //
 // The host flattens every member GEMM into output tiles (gemm, tile row,
-// tile column) in a chosen order -- as given, or longest-processing-time
-// first (largest K, then largest tile area) -- and uploads the member
-// descriptors and the work list.  A grid of (#CUs x work-groups per CU)
-// persistent work-groups then walks the list: statically (work-group b takes
-// items b, b + grid, ...) or dynamically (an atomic counter hands out the
-// next item; a one-thread kernel resets it inside the same graph).  Each
-// item runs the BF16 tile of the single-GEMM family (A row-major M x K, B
-// row-major K x N, FP32 C).
+// tile column, tile class) in a chosen order -- as given, or longest-
+// processing-time first (largest K) -- and uploads the member descriptors
+// and the work list.  Members with M * N at most a threshold take a smaller
+// tile than the rest (the two tiles of a kernel have the same number of
+// waves), so small members are not padded out to the large tile.  A grid of
+// (#CUs x work-groups per CU) persistent work-groups then walks the list:
+// statically (work-group b takes items b, b + grid, ...) or dynamically (an
+// atomic counter hands out the next item; a one-thread kernel resets it
+// inside the same graph).  Each item runs a BF16 tile of the single-GEMM
+// family (A row-major M x K, B row-major K x N, FP32 C): through LDS DMA when
+// both member operands have rows on 16-byte boundaries (their rows are then
+// read up to the next 16-byte boundary, within the leading dimension), else
+// register-staged.
 //
-// The autotuner searches (tile configuration, schedule, order, work-groups
-// per CU) by successive halving on the real workload: every candidate's
-// graph is timed, the faster half kept, the repetitions doubled, until one
-// remains.
+// The autotuner searches (tile pair, small-member threshold, schedule,
+// order, work-groups per CU) by successive halving on the real workload:
+// every candidate's graph is timed, the faster half kept, the repetitions
+// doubled, until one remains.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -22,7 +27,7 @@
 #include <numeric>
 #include <vector>
 
-#include "gemm_lp.hpp"
+#include "gemm_lp_dma.hpp"
 #include "kt_internal.hpp"
 
 namespace kt {
@@ -32,20 +37,38 @@ struct GroupDesc {
   const void* B;
   float* C;
   int64_t M, N, K, lda, ldb, ldc;
-  int32_t vecA, vecB;
+  int32_t vecA, vecB;   // register-path alignment modes
+  int32_t dma, pad;     // 1: both operands take the DMA pipeline
 };
 
 struct WorkItem {
-  int32_t g, tm, tn, pad;
+  int32_t g, tm, tn, cls;   // cls 0: the large tile, 1: the small tile
 };
 
 template <int BM, int BN, int T, int BK>
+struct GroupTile {
+  static constexpr int NT = BM * BN / (T * T);
+  static constexpr int L1 = GemmLpCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES;
+  static constexpr int L2 = LpDmaCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES;
+  static constexpr int LDS = L1 > L2 ? L1 : L2;
+
+  __device__ __forceinline__ static void run(const GemmArgs& a, int tm, int tn, bool dma,
+                                             char* lds) {
+    if (dma) lp_dma_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, lds);
+    else lp_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, reinterpret_cast<uint16_t*>(lds));
+  }
+};
+
+template <int BM, int BN, int T, int BK, int SM, int SN, int ST, int SK>
 __global__ void __launch_bounds__(BM * BN / (T * T))
 grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restrict__ work,
                     int32_t n_work, float alpha, float beta, int32_t dynamic,
                     uint32_t* __restrict__ counter, uint32_t* __restrict__ visits) {
-  using Cfg = GemmLpCfg<2, BM, BN, T, BK, 0, 0>;
-  __shared__ __attribute__((aligned(16))) uint16_t lds[Cfg::LDS_BYTES / 2];
+  using Big = GroupTile<BM, BN, T, BK>;
+  using Small = GroupTile<SM, SN, ST, SK>;
+  static_assert(Big::NT == Small::NT, "both tiles of a grouped kernel have the same waves");
+  constexpr int LDS = Big::LDS > Small::LDS ? Big::LDS : Small::LDS;
+  __shared__ __attribute__((aligned(16))) char lds[LDS];
   __shared__ int32_t s_w;
   int32_t w = blockIdx.x;
   for (;;) {
@@ -66,7 +89,8 @@ grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restr
     a.scaleA = nullptr; a.scaleB = nullptr;
     a.vecA = d.vecA; a.vecB = d.vecB;
     a.tiles_m = 0; a.tiles_n = 0;
-    lp_tile<2, BM, BN, T, BK, 0, 0>(a, it.tm, it.tn, 0, lds);
+    if (it.cls == 0) Big::run(a, it.tm, it.tn, d.dma != 0, lds);
+    else Small::run(a, it.tm, it.tn, d.dma != 0, lds);
     if (visits && threadIdx.x == 0) atomicAdd(&visits[w], 1u);
     __syncthreads();   // LDS and s_w are reused by the next item
     if (!dynamic) w += gridDim.x;
@@ -79,40 +103,52 @@ typedef void (*GroupedKernel)(const GroupDesc*, const WorkItem*, int32_t, float,
                               uint32_t*, uint32_t*);
 
 struct GroupedVariant {
-  int bm, bn, t, bk;
+  int bm, bn, t, bk;       // large tile
+  int sm, sn, st, sk;      // small tile (same waves)
   GroupedKernel fn;
 };
 
-// Tile configurations the grouped kernel is compiled for (a subset of the
-// BF16 configuration space).
+#define KT_GV(a, b, c, d, e, f, g, h) {a, b, c, d, e, f, g, h, grouped_bf16_kernel<a, b, c, d, e, f, g, h>}
+// Tile pairs the grouped kernel is compiled for (members of the BF16
+// configuration space).
 static const GroupedVariant kGroupedVariants[] = {
-    {64, 64, 4, 64, grouped_bf16_kernel<64, 64, 4, 64>},
-    {128, 64, 4, 64, grouped_bf16_kernel<128, 64, 4, 64>},
-    {64, 128, 4, 64, grouped_bf16_kernel<64, 128, 4, 64>},
-    {128, 128, 4, 32, grouped_bf16_kernel<128, 128, 4, 32>},
-    {128, 128, 8, 32, grouped_bf16_kernel<128, 128, 8, 32>},
-    {128, 128, 8, 64, grouped_bf16_kernel<128, 128, 8, 64>},
-    {256, 128, 8, 32, grouped_bf16_kernel<256, 128, 8, 32>},
-    {128, 256, 8, 32, grouped_bf16_kernel<128, 256, 8, 32>},
+    KT_GV(128, 128, 8, 64, 64, 64, 4, 64),
+    KT_GV(128, 128, 8, 32, 64, 64, 4, 32),
+    KT_GV(256, 128, 8, 32, 128, 64, 4, 32),
+    KT_GV(128, 256, 8, 32, 64, 128, 4, 32),
+    KT_GV(256, 256, 8, 64, 128, 128, 4, 64),
+    KT_GV(64, 64, 4, 64, 32, 32, 2, 64),
 };
+#undef KT_GV
 static constexpr int kNumVariants = sizeof(kGroupedVariants) / sizeof(kGroupedVariants[0]);
 
-static const GroupedVariant* variant_for(Ctx* h, int32_t config_id) {
-  if (config_id < 0 || config_id >= (int32_t)h->configs[KT_BF16].size()) return nullptr;
-  const ConfigDef& c = h->configs[KT_BF16][config_id];
+static int32_t config_id_of(Ctx* h, int bm, int bn, int t, int bk) {
+  for (int32_t i = 0; i < (int32_t)h->configs[KT_BF16].size(); ++i) {
+    const ConfigDef& c = h->configs[KT_BF16][i];
+    if (c.bm == bm && c.bn == bn && c.t == t && c.bk == bk) return i;
+  }
+  return -1;
+}
+
+// The compiled pair for (large, small) configuration ids; small -1 matches
+// any pair with that large tile (the small tile then goes unused).
+static const GroupedVariant* variant_for(Ctx* h, int32_t big, int32_t small) {
+  const int32_t n = (int32_t)h->configs[KT_BF16].size();
+  if (big < 0 || big >= n || small < -1 || small >= n) return nullptr;
   for (int i = 0; i < kNumVariants; ++i) {
     const GroupedVariant& v = kGroupedVariants[i];
-    if (v.bm == c.bm && v.bn == c.bn && v.t == c.t && v.bk == c.bk) return &v;
+    if (config_id_of(h, v.bm, v.bn, v.t, v.bk) != big) continue;
+    if (small < 0 || config_id_of(h, v.sm, v.sn, v.st, v.sk) == small) return &v;
   }
   return nullptr;
 }
 
 static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Smallest tile of any variant bounds the work list length.
+// Smallest tile of any variant (32 x 32) bounds the work list length.
 static int64_t max_work_items(const kt_shape* s, int32_t n) {
   int64_t tot = 0;
-  for (int32_t i = 0; i < n; ++i) tot += cdiv(s[i].M, 64) * cdiv(s[i].N, 64);
+  for (int32_t i = 0; i < n; ++i) tot += cdiv(s[i].M, 32) * cdiv(s[i].N, 32);
   return tot;
 }
 
@@ -130,7 +166,8 @@ using namespace kt;
 namespace kt {
 
 static kt_status validate_group(Ctx* h, kt_dtype dtype, const kt_shape* shapes, int32_t n,
-                                const void* const* A, const void* const* B, float* const* C) {
+                                const void* const* A, const void* const* B, float* const* C,
+                                const int64_t* ld) {
   if (dtype != KT_BF16) return fail(h, KT_EUNSUPPORTED, "grouped GEMM supports BF16 inputs");
   if (n < 0 || (n > 0 && (!shapes || !A || !B || !C))) return fail(h, KT_EINVAL, "bad group arrays");
   for (int32_t i = 0; i < n; ++i) {
@@ -140,16 +177,32 @@ static kt_status validate_group(Ctx* h, kt_dtype dtype, const kt_shape* shapes, 
       return fail(h, KT_EUNSUPPORTED, "grouped members must be batch 1, transA = transB = 0");
     if (s.M > 0 && s.N > 0 && (!C[i] || (s.K > 0 && (!A[i] || !B[i]))))
       return fail(h, KT_EINVAL, "NULL member pointer");
+    if (ld && (ld[3 * i] < std::max<int64_t>(s.K, 1) || ld[3 * i + 1] < std::max<int64_t>(s.N, 1) ||
+               ld[3 * i + 2] < std::max<int64_t>(s.N, 1)))
+      return fail(h, KT_EINVAL, "member leading dimension below its row length");
   }
   return KT_OK;
 }
 
+// Member operand alignment: the register pipeline's mode and whether the
+// DMA pipeline may read the operand (rows on 16-byte boundaries and the row's
+// last 16-byte chunk within the leading dimension: member rows are allocated
+// in full, so reading up to the next 16-byte boundary stays inside them).
+static int32_t member_vec(const void* p, int64_t ld) {
+  if ((uintptr_t)p % 4 != 0) return LP_ALIGN_NONE;
+  return ld % 2 == 0 ? LP_ALIGN_ROWS : LP_ALIGN_BASE;
+}
+static bool member_dma(const void* p, int64_t ld, int64_t ext) {
+  return (uintptr_t)p % 16 == 0 && ld % 8 == 0 && ext >= 8 && ld >= (ext + 7) / 8 * 8;
+}
+
 static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const void* const* A,
-                            const void* const* B, float* const* C, float alpha, float beta,
-                            const kt_grouped_opts& o, void* ws, size_t ws_bytes, hipStream_t stream,
-                            kt_grouped_plan_s** out) {
-  const GroupedVariant* v = variant_for(h, o.config_id);
-  if (!v) return fail(h, KT_EUNSUPPORTED, "BF16 configuration not compiled for the grouped kernel");
+                            const void* const* B, float* const* C, const int64_t* ld, float alpha,
+                            float beta, const kt_grouped_opts& o, void* ws, size_t ws_bytes,
+                            hipStream_t stream, kt_grouped_plan_s** out) {
+  const GroupedVariant* v = variant_for(h, o.config_id, o.small_config_id);
+  if (!v) return fail(h, KT_EUNSUPPORTED, "BF16 tile pair not compiled for the grouped kernel");
+  if (o.small_max_area < 0) return fail(h, KT_EINVAL, "negative small-member area");
   if (o.schedule < 0 || o.schedule > 1 || o.order < 0 || o.order > 1 || o.wgs_per_cu < 1 || o.wgs_per_cu > 4)
     return fail(h, KT_EINVAL, "bad grouped options");
   const size_t need = a256((size_t)n * sizeof(GroupDesc)) + a256((size_t)max_work_items(shapes, n) * sizeof(WorkItem)) + 256;
@@ -160,9 +213,13 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
     GroupDesc& d = descs[i];
     d.A = A[i]; d.B = B[i]; d.C = C[i];
     d.M = s.M; d.N = s.N; d.K = s.K;
-    d.lda = std::max<int64_t>(s.K, 1); d.ldb = std::max<int64_t>(s.N, 1); d.ldc = std::max<int64_t>(s.N, 1);
-    d.vecA = ((uintptr_t)A[i] % 4 != 0) ? 0 : (d.lda % 2 == 0 ? 2 : 1);
-    d.vecB = ((uintptr_t)B[i] % 4 != 0) ? 0 : (d.ldb % 2 == 0 ? 2 : 1);
+    d.lda = ld ? ld[3 * i] : std::max<int64_t>(s.K, 1);
+    d.ldb = ld ? ld[3 * i + 1] : std::max<int64_t>(s.N, 1);
+    d.ldc = ld ? ld[3 * i + 2] : std::max<int64_t>(s.N, 1);
+    d.vecA = member_vec(A[i], d.lda);
+    d.vecB = member_vec(B[i], d.ldb);
+    d.dma = s.K > 0 && member_dma(A[i], d.lda, s.K) && member_dma(B[i], d.ldb, s.N);
+    d.pad = 0;
   }
   std::vector<int32_t> gorder(n);
   std::iota(gorder.begin(), gorder.end(), 0);
@@ -172,9 +229,11 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
   for (int32_t g : gorder) {
     const kt_shape& s = shapes[g];
     if (s.M == 0 || s.N == 0) continue;
-    const int tmn = (int)cdiv(s.M, v->bm), tnn = (int)cdiv(s.N, v->bn);
+    const int cls = (o.small_config_id >= 0 && s.M * s.N <= o.small_max_area) ? 1 : 0;
+    const int bm = cls ? v->sm : v->bm, bn = cls ? v->sn : v->bn;
+    const int tmn = (int)cdiv(s.M, bm), tnn = (int)cdiv(s.N, bn);
     for (int tm = 0; tm < tmn; ++tm)
-      for (int tn = 0; tn < tnn; ++tn) work.push_back(WorkItem{g, tm, tn, 0});
+      for (int tn = 0; tn < tnn; ++tn) work.push_back(WorkItem{g, tm, tn, cls});
   }
   char* w = (char*)ws;
   GroupDesc* d_desc = (GroupDesc*)w;
@@ -228,11 +287,9 @@ static void plan_free(kt_grouped_plan_s* p) {
 static kt_grouped_opts default_grouped_opts(Ctx* h) {
   kt_grouped_opts o;
   memset(&o, 0, sizeof o);
-  o.config_id = -1;
-  for (int32_t i = 0; i < (int32_t)h->configs[KT_BF16].size(); ++i) {
-    const ConfigDef& c = h->configs[KT_BF16][i];
-    if (c.bm == 128 && c.bn == 128 && c.t == 8 && c.bk == 32) o.config_id = i;
-  }
+  o.config_id = config_id_of(h, 128, 128, 8, 32);
+  o.small_config_id = config_id_of(h, 64, 64, 4, 32);
+  o.small_max_area = 256 * 256;
   o.schedule = 1;
   o.order = 1;
   o.wgs_per_cu = 2;
@@ -257,18 +314,19 @@ kt_status kt_grouped_num_candidates(int32_t* n) {
 
 kt_status kt_grouped_plan_create(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t n,
                                  const void* const* A, const void* const* B, float* const* C,
-                                 float alpha, float beta, const kt_grouped_opts* opts,
-                                 void* workspace, size_t ws_bytes, void* stream,
-                                 kt_grouped_plan* out) {
+                                 const int64_t* ld, float alpha, float beta,
+                                 const kt_grouped_opts* opts, void* workspace, size_t ws_bytes,
+                                 void* stream, kt_grouped_plan* out) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!need_device(h)) return KT_EINVAL;
   if (!out) return fail(h, KT_EINVAL, "NULL plan output");
-  kt_status s = validate_group(h, dtype, shapes, n, A, B, C);
+  kt_status s = validate_group(h, dtype, shapes, n, A, B, C, ld);
   if (s != KT_OK) return s;
   kt_grouped_opts o = opts ? *opts : (h->grouped_tuned ? h->grouped_best : default_grouped_opts(h));
   kt_grouped_plan_s* p = nullptr;
-  s = plan_build(h, shapes, n, A, B, C, alpha, beta, o, workspace, ws_bytes, (hipStream_t)stream, &p);
+  s = plan_build(h, shapes, n, A, B, C, ld, alpha, beta, o, workspace, ws_bytes,
+                 (hipStream_t)stream, &p);
   if (s != KT_OK) return s;
   *out = p;
   return KT_OK;
@@ -297,12 +355,12 @@ kt_status kt_grouped_plan_destroy(kt_grouped_plan plan) {
 }
 
 kt_status kt_grouped_gemm(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t n,
-                          const void* const* A, const void* const* B, float* const* C, float alpha,
-                          float beta, const kt_grouped_opts* opts, void* workspace, size_t ws_bytes,
-                          void* stream) {
+                          const void* const* A, const void* const* B, float* const* C,
+                          const int64_t* ld, float alpha, float beta, const kt_grouped_opts* opts,
+                          void* workspace, size_t ws_bytes, void* stream) {
   kt_grouped_plan p = nullptr;
-  kt_status s = kt_grouped_plan_create(hh, dtype, shapes, n, A, B, C, alpha, beta, opts, workspace,
-                                       ws_bytes, stream, &p);
+  kt_status s = kt_grouped_plan_create(hh, dtype, shapes, n, A, B, C, ld, alpha, beta, opts,
+                                       workspace, ws_bytes, stream, &p);
   if (s != KT_OK) return s;
   s = kt_grouped_plan_launch(hh, p, stream);
   Ctx* h = reinterpret_cast<Ctx*>(hh);
@@ -314,31 +372,33 @@ kt_status kt_grouped_gemm(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, 
 
 kt_status kt_autotune_grouped(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t n,
                               const void* const* A, const void* const* B, float* const* C,
-                              void* workspace, size_t ws_bytes, void* stream,
+                              const int64_t* ld, void* workspace, size_t ws_bytes, void* stream,
                               kt_grouped_opts* best, float* best_ms, int32_t* evaluations) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!need_device(h)) return KT_EINVAL;
-  kt_status s = validate_group(h, dtype, shapes, n, A, B, C);
+  kt_status s = validate_group(h, dtype, shapes, n, A, B, C, ld);
   if (s != KT_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   std::vector<kt_grouped_opts> cands;
+  static const int64_t kAreas[] = {0, 128 * 128, 256 * 256, 512 * 512};
   for (int vi = 0; vi < kNumVariants; ++vi) {
-    int32_t id = -1;
-    for (int32_t i = 0; i < (int32_t)h->configs[KT_BF16].size(); ++i) {
-      const ConfigDef& c = h->configs[KT_BF16][i];
-      const GroupedVariant& v = kGroupedVariants[vi];
-      if (c.bm == v.bm && c.bn == v.bn && c.t == v.t && c.bk == v.bk) id = i;
-    }
-    if (id < 0) continue;
-    for (int sched = 0; sched < 2; ++sched)
-      for (int order = 0; order < 2; ++order)
-        for (int wgs = 1; wgs <= 2; ++wgs) {
-          kt_grouped_opts o;
-          memset(&o, 0, sizeof o);
-          o.config_id = id; o.schedule = sched; o.order = order; o.wgs_per_cu = wgs;
-          cands.push_back(o);
-        }
+    const GroupedVariant& v = kGroupedVariants[vi];
+    const int32_t big = config_id_of(h, v.bm, v.bn, v.t, v.bk);
+    const int32_t small = config_id_of(h, v.sm, v.sn, v.st, v.sk);
+    if (big < 0 || small < 0) continue;
+    for (int64_t area : kAreas)
+      for (int sched = 0; sched < 2; ++sched)
+        for (int order = 0; order < 2; ++order)
+          for (int wgs = 1; wgs <= 2; ++wgs) {
+            kt_grouped_opts o;
+            memset(&o, 0, sizeof o);
+            o.config_id = big;
+            o.small_config_id = area > 0 ? small : -1;
+            o.small_max_area = area;
+            o.schedule = sched; o.order = order; o.wgs_per_cu = wgs;
+            cands.push_back(o);
+          }
   }
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
@@ -351,7 +411,7 @@ kt_status kt_autotune_grouped(kt_handle hh, kt_dtype dtype, const kt_shape* shap
   while (s == KT_OK) {
     for (int ci : alive) {
       kt_grouped_plan_s* p = nullptr;
-      s = plan_build(h, shapes, n, A, B, C, 1.f, 0.f, cands[ci], workspace, ws_bytes, st, &p);
+      s = plan_build(h, shapes, n, A, B, C, ld, 1.f, 0.f, cands[ci], workspace, ws_bytes, st, &p);
       if (s != KT_OK) break;
       e = hipGraphLaunch(p->exec, st);                   // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, st);

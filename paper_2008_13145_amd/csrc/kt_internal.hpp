@@ -72,6 +72,7 @@ struct Ctx {
   size_t gemm_ws_bytes = 0;
   void* noalloc_scratch = nullptr; // device address of the static split-K scratch
   bool forbid_alloc = false;       // set while an entry point that must not allocate runs
+  bool full_rows = false;          // caller: every operand row is allocated to its full ld
 };
 
 // Record an error message on the handle and return the status.
@@ -92,7 +93,7 @@ kt_status launch_gemm(Ctx* h, int dtype, const kt_shape* s, float alpha, const v
 
 // Alignment class of an operand (GemmArgs::vecA / vecB).
 int32_t operand_alignment(int dtype, const void* p, int64_t ld, int64_t stride, int64_t batch,
-                          int64_t ext);
+                          int64_t ext, bool full_rows);
 
 // Kernel ids: configurations 0 .. n_configs-1, then split-K variants.
 inline int32_t num_kernels(const Ctx* h, int dtype) {

@@ -14,26 +14,38 @@ from oracle import gemm as og
 pytestmark = pytest.mark.gpu
 
 
-def _group(h, torch, shapes, seed):
+def _group(h, torch, shapes, seed, padded=False):
     """Device BF16 operands (converted on the GPU from the seeded FP32
-    stream), FP32 outputs, and the host FP32 originals."""
-    A, B, C, host = [], [], [], []
+    stream), FP32 outputs, and the host FP32 originals.  padded: A and B rows
+    padded to a multiple of 8 elements (16 bytes), the padding holding BF16
+    NaNs that must never reach a stored output; returns the leading
+    dimensions too."""
+    A, B, C, host, ld = [], [], [], [], []
     for i, (M, N, K) in enumerate(shapes):
         sa, sb = synth.operand_seed(seed + i, 0), synth.operand_seed(seed + i, 1)
+        lda = (K + 7) // 8 * 8 if padded else K
+        ldb = (N + 7) // 8 * 8 if padded else N
         a32 = torch.empty(M * K, dtype=torch.float32, device="cuda")
         b32 = torch.empty(K * N, dtype=torch.float32, device="cuda")
         h.fill_uniform(a32, M * K, sa)
         h.fill_uniform(b32, K * N, sb)
-        a = torch.empty(M * K, dtype=torch.int16, device="cuda")
-        b = torch.empty(K * N, dtype=torch.int16, device="cuda")
-        h.convert_bf16(a32, M * K, a)
-        h.convert_bf16(b32, K * N, b)
+        a = torch.full((M * lda,), 0x7FC0, dtype=torch.int16, device="cuda")
+        b = torch.full((K * ldb,), 0x7FC0, dtype=torch.int16, device="cuda")
+        ta = torch.empty(M * K, dtype=torch.int16, device="cuda")
+        tb = torch.empty(K * N, dtype=torch.int16, device="cuda")
+        h.convert_bf16(a32, M * K, ta)
+        h.convert_bf16(b32, K * N, tb)
+        if M * K:
+            a.view(M, lda)[:, :K] = ta.view(M, K)
+        if K * N:
+            b.view(K, ldb)[:, :N] = tb.view(K, N)
         A.append(a)
         B.append(b)
         C.append(torch.full((M * N,), float("nan"), dtype=torch.float32, device="cuda"))
         host.append((sa, sb))
+        ld.append((max(lda, 1), max(ldb, 1), max(N, 1)))
     torch.cuda.synchronize()
-    return A, B, C, host
+    return (A, B, C, host, ld) if padded else (A, B, C, host)
 
 
 def _check_member(M, N, K, sa, sb, got, full=True, rows=None, cols=None):
@@ -70,16 +82,21 @@ def test_every_option_is_correct_and_covers_each_tile_once(gpu):
     n_cand = ctypes_candidates(kt)
     assert n_cand >= 6
     cfgs = h.configs(kt.BF16)
-    cand_ids = [cfgs.index(c) for c in [(64, 64, 4, 64), (128, 128, 8, 32), (256, 128, 8, 32)]]
+    pairs = [((64, 64, 4, 64), (32, 32, 2, 64)), ((128, 128, 8, 32), (64, 64, 4, 32)),
+             ((256, 128, 8, 32), (128, 64, 4, 32))]
+    cand_ids = [(cfgs.index(b), cfgs.index(sm)) for b, sm in pairs]
     first = None
-    for cid in cand_ids:
+    for cid, small in cand_ids:
         for sched in (0, 1):
             for order in (0, 1):
                 visits = torch.zeros(200000, dtype=torch.int32, device="cuda")
                 for c in C:
                     c.fill_(float("nan"))
+                # order 1 also sends members up to 128 x 128 outputs to the small tile
+                area = 128 * 128 if order else 0
                 plan = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
-                                      opts=kt.GroupedOpts(cid, sched, order, 2, visits.data_ptr()),
+                                      opts=kt.GroupedOpts(cid, small if area else -1, area, sched,
+                                                          order, 2, visits.data_ptr()),
                                       workspace=ws, ws_bytes=ws_bytes)
                 n_work, _ = h.grouped_info(plan)
                 h.grouped_launch(plan)
@@ -88,7 +105,7 @@ def test_every_option_is_correct_and_covers_each_tile_once(gpu):
                 assert (v[:n_work] == 1).all() and not v[n_work:].any()
                 h.grouped_destroy(plan)
                 outs = [c.cpu().numpy() for c in C]
-                if (cid, sched, order) == (cand_ids[0], 0, 0):
+                if (cid, sched, order) == (cand_ids[0][0], 0, 0):
                     for (M, N, K), (sa, sb), got in zip(shapes, host, outs):
                         if M and N:
                             if K == 0:
@@ -96,8 +113,8 @@ def test_every_option_is_correct_and_covers_each_tile_once(gpu):
                             else:
                                 _check_member(M, N, K, sa, sb, got)
                     first = outs
-                elif cid == cand_ids[0]:
-                    # every schedule and order computes each tile with the same code
+                elif cid == cand_ids[0][0] and order == 0:
+                    # every schedule computes each tile with the same code
                     for x, y in zip(outs, first):
                         assert np.array_equal(x, y, equal_nan=True)
                 else:
@@ -120,7 +137,9 @@ def test_graph_replays_match_first_run(gpu):
     ws_bytes = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for m, n, k in shapes])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     cid = h.configs(kt.BF16).index((128, 128, 8, 32))
-    plan = h.grouped_plan(shapes, A, B, C, 1.0, 0.0, opts=kt.GroupedOpts(cid, 1, 1, 2, None),
+    small = h.configs(kt.BF16).index((64, 64, 4, 32))
+    plan = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
+                          opts=kt.GroupedOpts(cid, small, 256 * 256, 1, 1, 2, None),
                           workspace=ws, ws_bytes=ws_bytes)
     h.grouped_launch(plan)
     torch.cuda.synchronize()
@@ -180,3 +199,78 @@ def test_rejects_unsupported_members(gpu):
     with pytest.raises(kt.KtError) as e:
         h.grouped_plan([(4, 4, 4)], [d], [d], [c], workspace=ws, ws_bytes=8)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("pair", [((128, 128, 8, 64), (64, 64, 4, 64)),
+                                  ((256, 256, 8, 64), (128, 128, 4, 64)),
+                                  ((64, 64, 4, 64), (32, 32, 2, 64))])
+def test_padded_members_take_the_dma_pipeline(gpu, pair):
+    """Members whose rows are padded to 16 bytes (padding full of NaNs) run
+    through LDS DMA, reading each row up to its 16-byte boundary: results
+    equal the dense-row (register-staged) plan bit for bit and the oracle."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    shapes = _small_shapes()[:24] + [(5, 3, 7), (64, 64, 8), (33, 17, 9)]
+    A, B, C, host, ld = _group(h, torch, shapes, 900, padded=True)
+    A2, B2, C2, _ = _group(h, torch, shapes, 900)
+    cfgs = h.configs(kt.BF16)
+    big, small = cfgs.index(pair[0]), cfgs.index(pair[1])
+    ws_bytes = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for m, n, k in shapes])
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    for area in (0, 256 * 256):
+        opts = kt.GroupedOpts(big, small if area else -1, area, 1, 1, 2, None)
+        for c in C + C2:
+            c.fill_(float("nan"))
+        p1 = h.grouped_plan(shapes, A, B, C, 1.0, 0.0, opts=opts, workspace=ws, ws_bytes=ws_bytes,
+                            ld=ld)
+        h.grouped_launch(p1)
+        torch.cuda.synchronize()
+        h.grouped_destroy(p1)
+        p2 = h.grouped_plan(shapes, A2, B2, C2, 1.0, 0.0, opts=opts, workspace=ws,
+                            ws_bytes=ws_bytes)
+        h.grouped_launch(p2)
+        torch.cuda.synchronize()
+        h.grouped_destroy(p2)
+        for (M, N, K), (sa, sb), x, y in zip(shapes, host, C, C2):
+            gx, gy = x.cpu().numpy(), y.cpu().numpy()
+            assert np.array_equal(gx.view(np.uint32), gy.view(np.uint32)), (M, N, K, area)
+            if M and N and K:
+                _check_member(M, N, K, sa, sb, gx)
+
+
+def test_padded_full_group_autotuned(gpu):
+    """The 512-member workload with rows padded to 16 bytes: autotuned, one
+    graph launch, every member checked on sampled rows and columns."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    shapes = synth.grouped_shapes()
+    A, B, C, host, ld = _group(h, torch, shapes, 1000, padded=True)
+    ws_bytes = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for m, n, k in shapes])
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    best, ms, evals = h.autotune_grouped(shapes, A, B, C, ws, ws_bytes, ld=ld)
+    assert evals >= 8 and ms > 0
+    for c in C:
+        c.fill_(float("nan"))
+    plan = h.grouped_plan(shapes, A, B, C, workspace=ws, ws_bytes=ws_bytes, ld=ld)
+    assert h.grouped_info(plan)[1] == best
+    h.grouped_launch(plan)
+    torch.cuda.synchronize()
+    h.grouped_destroy(plan)
+    rng = np.random.default_rng(6)
+    for i, ((M, N, K), (sa, sb)) in enumerate(zip(shapes, host)):
+        got = C[i].cpu().numpy()
+        assert not np.isnan(got).any()
+        rows = np.sort(rng.choice(M, min(M, 4), replace=False))
+        cols = np.sort(rng.choice(N, min(N, 4), replace=False))
+        _check_member(M, N, K, sa, sb, got, full=False, rows=rows, cols=cols)
+
+
+def test_member_leading_dimensions_checked(gpu):
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    d = torch.zeros(64, dtype=torch.int16, device="cuda")
+    c = torch.zeros(64, dtype=torch.float32, device="cuda")
+    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    with pytest.raises(kt.KtError) as e:
+        h.grouped_plan([(4, 4, 4)], [d], [d], [c], workspace=ws, ws_bytes=4096, ld=[(3, 4, 4)])
+    assert e.value.status == -1
