@@ -221,11 +221,11 @@ def main(argv=None):
                     config_ids=sorted({h.get_kernel(c)[1] for c in chosen}),
                     norm=res["norm_name"], train_ceiling=res["train_ceiling"], seed=synth.SEED,
                     n_init=10, max_iter=300, table=os.path.relpath(a.table, HERE),
-                    device=meta.get("device"), inertia=res["inertia"])
+                    device=meta.get("device"))
         os.makedirs(os.path.dirname(a.spec), exist_ok=True)
         with open(a.spec, "w") as f:
             json.dump(spec, f, indent=1)
-        print("chosen", chosen, spec["configs"], flush=True)
+        print("chosen", chosen, spec["kernels"], flush=True)
         if not a.no_build:
             build.build(f32_ids=spec["config_ids"], lp_ids=[], out=a.out, tag="deploy",
                         verbose=True)

@@ -28,14 +28,26 @@ def deploy(gpu):
     hd.close()
 
 
+def _config_ids(spec):
+    """Configurations the deploy build holds: those of the chosen kernels (a
+    split-K variant runs its base configuration's code)."""
+    return set(spec.get("config_ids", spec["chosen"]))
+
+
 def test_only_chosen_configs_compiled(deploy, kt):
     spec, hd = deploy
     chosen = set(spec["chosen"])
     assert len(chosen) == spec["k"]
+    cfg_ids = _config_ids(spec)
+    assert cfg_ids == {hd.get_kernel(c)[1] for c in chosen}
     for cid in range(hd.num_configs()):
         for ta, tb in synth.LAYOUTS:
-            assert hd.config_compiled(cid, ta, tb) == (cid in chosen)
-    assert [list(hd.get_config(c)) for c in spec["chosen"]] == spec["configs"]
+            assert hd.config_compiled(cid, ta, tb) == (cid in cfg_ids)
+    if "kernels" in spec:
+        assert [list(hd.get_kernel(c)[0]) for c in spec["chosen"]] == spec["kernels"]
+    # every split-K variant of a kept configuration is available, no other
+    for v in range(hd.num_configs(), hd.num_kernels()):
+        assert hd.config_compiled(v, 0, 0) == (hd.get_kernel(v)[1] in cfg_ids)
     assert os.path.getsize(DEPLOY) < os.path.getsize(kt.LIB_PATH)
 
 
@@ -62,7 +74,7 @@ def test_deploy_rejects_pruned_config_and_selects(deploy, gpu):
     import paper_2008_13145_amd as kt
     spec, hd = deploy
     h, torch = gpu
-    other = next(c for c in range(hd.num_configs()) if c not in spec["chosen"])
+    other = next(c for c in range(hd.num_configs()) if c not in _config_ids(spec))
     d = torch.zeros(64 * 64, dtype=torch.float32, device="cuda")
     st = hd.gemm_raw(kt.F32, kt.shape(8, 8, 8), 1.0, d, 8, 0, d, 8, 0, 0.0, d, 8, 0,
                      config_id=other, check=False)
@@ -70,7 +82,7 @@ def test_deploy_rejects_pruned_config_and_selects(deploy, gpu):
     # a selector fitted over the deployed set picks only deployed kernels
     problems = synth.sweep_problems(40, 31)
     rng = np.random.default_rng(0)
-    T = rng.integers(1000, 100000, size=(len(problems), hd.num_configs())).astype(np.int64)
+    T = rng.integers(1000, 100000, size=(len(problems), hd.num_kernels())).astype(np.int64)
     hd.fit_selector(kt.SEL_DT_A, problems, T, spec["chosen"])
     for p in problems[:20]:
         assert hd.select(*p) in spec["chosen"]

@@ -279,3 +279,38 @@ def test_lowp_sweep(gpu):
         T = h.sweep(problems, ws, ws_bytes, config_ids=[0, 10, 30, 58], target_ms=0.2,
                     max_reps=10, dtype=dtype)
         assert (T > 0).all()
+
+
+@pytest.mark.parametrize("cfg_t,K", [(4, 64), (2, 128)])
+def test_fp8_mfma_accumulation_error_measured(gpu, cfg_t, K):
+    """The evidence behind the FP8 bounds: one K step of exactly one MFMA
+    (64 deep for the 32x32 blocks, 128 for the 16x16 ones) on random e4m3
+    codes with unit scales, against the exact sum of the products (every
+    product and partial sum is exact in FP64).  The error per element stays
+    within 2^-11 of the sum of the magnitudes of its terms (the accumulation
+    inside the instruction is not full FP32; measured about 2^-12), which
+    over K / depth instructions gives the K-linear bound the tests use."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    M = N = 64
+    rng = np.random.default_rng(31 + K)
+    codes_a = rng.integers(0, 256, size=(M, K)).astype(np.uint8)
+    codes_b = rng.integers(0, 256, size=(N, K)).astype(np.uint8)
+    for c in (codes_a, codes_b):
+        c[(c & 0x7F) == 0x7F] = 0x38          # no NaN codes (0x38 = 1.0)
+    a = cv.e4m3_decode(codes_a).astype(np.float64)
+    b = cv.e4m3_decode(codes_b).astype(np.float64)
+    exact = a @ b.T
+    mag = np.abs(a) @ np.abs(b).T
+    dA = torch.from_numpy(codes_a).cuda()
+    dB = torch.from_numpy(codes_b).cuda()
+    sc = torch.ones(2, dtype=torch.float32, device="cuda")
+    cfgs = h.configs(FP8)
+    cid = next(i for i, c in enumerate(cfgs) if c[2] == cfg_t and c[3] == K and c[0] == c[1] == 64)
+    dC = torch.full((M, N), float("nan"), device="cuda")
+    h.gemm_raw(FP8, kt.shape(M, N, K, 1, 0, 1), 1.0, dA, K, 0, dB, K, 0, 0.0, dC, N, 0,
+               scaleA=sc[0:].data_ptr(), scaleB=sc[1:].data_ptr(), config_id=cid)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.float64)
+    ratio = np.abs(got - exact) / np.maximum(mag, 1e-300)
+    assert ratio.max() <= 2.0 ** -11, float(np.log2(ratio.max()))
