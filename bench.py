@@ -180,10 +180,12 @@ def splitk_section(kt, h, torch, T, problems, plans, chosen, stream, reps=5):
     exhaustive-best plain launch against the best split-K launch over splits
     {2, 4, 8, 16} x (that configuration and the k deployed ones), both timed
     live on resident operands (mean of `reps` launches after one warm-up)."""
-    cfgs = h.kernels()
+    cfgs = h.configs()
+    n_plain = len(cfgs)
+    Tp = T[:, :n_plain]          # the configurations' columns (split-K variants are timed here)
     rows = []
     for r, (M, N, K, bt, ta, tb) in enumerate(problems):
-        bm, bn = cfgs[int(np.argmin(T[r]))][:2]
+        bm, bn = cfgs[int(np.argmin(Tp[r]))][:2]
         if K >= 512 and -(-M // bm) * -(-N // bn) * bt < 256:
             rows.append(r)
     if not rows:
@@ -205,12 +207,12 @@ def splitk_section(kt, h, torch, T, problems, plans, chosen, stream, reps=5):
     t_plain, t_split, best_pick = [], [], []
     for r in rows:
         pl = plans[r]
-        best = int(np.argmin(T[r]))
+        best = int(np.argmin(Tp[r]))
         t_plain.append(timed(lambda: h.gemm_raw(kt.F32, pl[0], 1.0, pl[1], pl[2], pl[3], pl[4],
                                                 pl[5], pl[6], 0.0, pl[7], pl[8], pl[9],
                                                 config_id=best, stream=stream)))
         cand = []
-        for cid in dict.fromkeys([best] + list(chosen)):
+        for cid in dict.fromkeys([best] + [h.get_kernel(c)[1] for c in chosen]):
             for sp in (2, 4, 8, 16):
                 us = timed(lambda: h.gemm_splitk_raw(kt.F32, pl[0], sp, 1.0, pl[1], pl[2], pl[3],
                                                      pl[4], pl[5], pl[6], 0.0, pl[7], pl[8],
@@ -771,7 +773,7 @@ def square_lp_section(kt, h, torch, synth, stream, n=4096, reps=10):
         for ta, tb in synth.LAYOUTS:
             lda, ldb = (M if ta else K), (K if tb else N)
             shp = kt.shape(M, N, K, 1, ta, tb)
-            assert h.lp_pipeline_dma(dt, shp, A, lda, 0, B, ldb, 0)
+            assert h.dma_pipeline(dt, shp, A, lda, 0, B, ldb, 0)
 
             def run(cid):
                 h.gemm_raw(dt, shp, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, N, 0,
@@ -1058,6 +1060,33 @@ def main(argv=None):
     _log(f"bench: deployed selector {sel_name} (validation scores {val_scores})")
     picks_all = [h.select(*p) for p in problems]       # fallback timing happens here, once
     deployed_te = ev_picks([picks_all[r] for r in te_rows])
+    # the split-K kernel family (section 3's kernel type for deep, under-
+    # filled products): where it is the exhaustive best, where the deployed
+    # selector runs it, and the held-out deep-K under-filled rows
+    n_cfg_plain = h.num_configs()
+    best_col = T.argmin(axis=1)
+
+    def underfilled(r):
+        M_, N_, K_, b_ = problems[r][:4]
+        bm_, bn_ = kernels[int(best_col[r])][:2]
+        return K_ >= 512 and -(-M_ // bm_) * -(-N_ // bn_) * b_ < 256
+    uf_te = [r for r in te_rows if underfilled(r)]
+    split_family = {
+        "kernels": n_cfg - n_cfg_plain,
+        "chosen_split_kernels": [list(kernels[c]) for c in chosen if c >= n_cfg_plain],
+        "rows_split_best": int((best_col >= n_cfg_plain).sum()),
+        "rows_split_best_by_5pct": int(sum(1 for r in range(n_prob) if best_col[r] >= n_cfg_plain and
+                                           T[r, :n_cfg_plain].min() > 1.05 * T[r].min())),
+        "test_rows_running_split": int(sum(1 for r in te_rows if picks_all[r] >= n_cfg_plain)),
+        "underfilled_deep_k_test_rows": len(uf_te)}
+    if uf_te:
+        split_family["underfilled_deep_k_test_pct_of_optimal"] = round(
+            100 * ev_picks([picks_all[r] for r in uf_te], uf_te)["geomean"], 2)
+        split_family["underfilled_deep_k_test_ceiling_pct"] = round(
+            100 * ev_ceiling(chosen, uf_te)["geomean"], 2)
+        split_family["underfilled_deep_k_test_ceiling_chosen_minus_split_kernels_pct"] = round(
+            100 * h.evaluate(T[:, :n_cfg_plain], rows=uf_te,
+                             chosen=[c for c in chosen if c < n_cfg_plain] or [0])["geomean"], 2)
     box = h.selector_info()
     n_outside = sum(1 for r in te_rows if any(
         not (box["box_lo"][f] <= problems[r][f] <= box["box_hi"][f]) for f in range(4)))
@@ -1170,6 +1199,7 @@ def main(argv=None):
             "mean": round(100 * deployed_te["mean"], 2), "min": round(100 * deployed_te["min"], 2),
             "frac_ge_0.9": round(deployed_te["frac_ge_0_9"], 4),
             "test_rows_outside_training_range": n_outside, "target_met": deployed_te["geomean"] >= 0.9},
+        "split_k_family": split_family,
         "pct_of_exhaustive_best": {
             "geomean_all_rows_table_in_sample": round(100 * sel_all["geomean"], 2),
             "time_weighted_live_in_sample": round(100 * pct_exh_live, 2),

@@ -177,7 +177,7 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
                   const float* scaleA, const float* scaleB,
                   int32_t config_id, void* stream);
 
-/* Which pipeline the BF16 / FP8 kernels take for these operands (host only,
+/* Which pipeline the GEMM kernels take for these operands (host only,
  * nothing launched): *dma = 1 when every row of A and B starts on a 16-byte
  * boundary (base, leading dimension and, for batch > 1, batch stride) and no
  * 16-byte chunk read leaves an operand: its contiguous extent (K for an
@@ -185,8 +185,13 @@ kt_status kt_gemm(kt_handle h, kt_dtype in_dtype, const kt_shape* s, float alpha
  * chunks or, after kt_set_full_rows(h, 1), at least one chunk with the
  * leading dimension reaching the next 16-byte boundary -- tiles then move
  * from HBM to LDS by LDS DMA with several stages in flight; otherwise 0
- * (register-staged loads; same results).  Always 0 for KT_F32. */
-kt_status kt_lp_pipeline(kt_handle h, kt_dtype dtype, const kt_shape* s, const void* A,
+ * (register-staged loads).  BF16 / FP8: every configuration has both
+ * pipelines and they give the same bits.  FP32: configurations with t >= 2
+ * whose A and B tiles are whole KiB (bm * bk, bn * bk multiples of 256) have
+ * the DMA pipeline; it sums K in another order than the register-staged one
+ * (results within the same bound, not bit-identical); the others always run
+ * register-staged. */
+kt_status kt_dma_pipeline(kt_handle h, kt_dtype dtype, const kt_shape* s, const void* A,
                          int64_t lda, int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
                          int32_t* dma);
 /* Promise (enabled = 1) that every BF16 / FP8 operand later passed to this

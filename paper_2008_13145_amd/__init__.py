@@ -114,7 +114,7 @@ _SIGS = {
     "kt_kernel_workspace_bytes": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_i32,
                                           ctypes.POINTER(c_sz)]),
     "kt_set_workspace": (c_i32, [c_vp, c_vp, c_sz]),
-    "kt_lp_pipeline": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i64, c_i64, c_vp, c_i64,
+    "kt_dma_pipeline": (c_i32, [c_vp, c_i32, ctypes.POINTER(Shape), c_vp, c_i64, c_i64, c_vp, c_i64,
                                c_i64, ctypes.POINTER(c_i32)]),
     "kt_set_full_rows": (c_i32, [c_vp, c_i32]),
     "kt_sweep_workspace_bytes": (c_i32, [ctypes.POINTER(Shape), c_i32, c_i32, ctypes.POINTER(c_sz)]),
@@ -300,10 +300,10 @@ class Handle:
                                                      int(id), ctypes.byref(b)))
         return b.value
 
-    def lp_pipeline_dma(self, dtype, shp: Shape, A, lda, sA, B, ldb, sB) -> bool:
+    def dma_pipeline(self, dtype, shp: Shape, A, lda, sA, B, ldb, sB) -> bool:
         """True when BF16 / FP8 kernels run these operands through the LDS DMA pipeline."""
         v = c_i32()
-        self._check(self.L.kt_lp_pipeline(self.h, int(dtype), ctypes.byref(shp), _ptr(A), int(lda),
+        self._check(self.L.kt_dma_pipeline(self.h, int(dtype), ctypes.byref(shp), _ptr(A), int(lda),
                                           int(sA), _ptr(B), int(ldb), int(sB), ctypes.byref(v)))
         return bool(v.value)
 

@@ -127,7 +127,7 @@ def kernels(cfgs):
 
 
 DTYPES = (  # (name, config list, launcher template)
-    ("f32", f32_configs, "launch_gemm_f32<{bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_f32.hpp"),
+    ("f32", f32_configs, "launch_gemm_f32<{bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_f32_dma.hpp"),
     ("bf16", bf16_configs, "launch_gemm_lp<2, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp_dma.hpp"),
     ("fp8", fp8_configs, "launch_gemm_lp<1, {bm}, {bn}, {t}, {bk}, {ta}, {tb}>", "gemm_lp_dma.hpp"),
 )

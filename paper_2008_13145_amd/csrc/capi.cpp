@@ -84,8 +84,7 @@ static int elem_bytes(int dtype) { return dtype == KT_F32 ? 4 : dtype == KT_BF16
 // loaded through a realigned window), 0 = neither (element loads); 3 = every
 // row on a 16-byte boundary and whole 16-byte chunks along the contiguous
 // extent `ext` (K for an operand stored K-contiguous, M or N otherwise),
-// which takes the low-precision DMA pipeline.  FP32 rows are always 4-byte
-// aligned (2).
+// which takes the DMA pipeline.
 int32_t operand_alignment(int dtype, const void* p, int64_t ld, int64_t stride, int64_t batch,
                           int64_t ext, bool full_rows) {
   const int eb = elem_bytes(dtype);
@@ -95,7 +94,7 @@ int32_t operand_alignment(int dtype, const void* p, int64_t ld, int64_t stride, 
   // with rows allocated in full, a row's last chunk may end anywhere within
   // the leading dimension
   const bool ext_ok = ext % ce == 0 || (full_rows && ext >= ce && ld >= (ext + ce - 1) / ce * ce);
-  if (eb < 4 && (uintptr_t)p % 16 == 0 && ld % ce == 0 && (batch <= 1 || stride % ce == 0) && ext_ok)
+  if ((uintptr_t)p % 16 == 0 && ld % ce == 0 && (batch <= 1 || stride % ce == 0) && ext_ok)
     return 3;
   return 2;
 }
@@ -300,15 +299,14 @@ kt_status kt_gemm(kt_handle hh, kt_dtype in_dtype, const kt_shape* s, float alph
                     strideC, scaleA, scaleB, id, h->gemm_ws, h->gemm_ws_bytes, (hipStream_t)stream);
 }
 
-kt_status kt_lp_pipeline(kt_handle hh, kt_dtype dtype, const kt_shape* s, const void* A,
+kt_status kt_dma_pipeline(kt_handle hh, kt_dtype dtype, const kt_shape* s, const void* A,
                          int64_t lda, int64_t strideA, const void* B, int64_t ldb, int64_t strideB,
                          int32_t* dma) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (!s || !dma) return fail(h, KT_EINVAL, "NULL argument");
   if ((int)dtype < 0 || (int)dtype >= NUM_DTYPES) return fail(h, KT_EINVAL, "bad dtype");
-  *dma = dtype != KT_F32 &&
-         operand_alignment(dtype, A, lda, strideA, s->batch, s->transA ? s->M : s->K,
+  *dma = operand_alignment(dtype, A, lda, strideA, s->batch, s->transA ? s->M : s->K,
                            h->full_rows) == 3 &&
          operand_alignment(dtype, B, ldb, strideB, s->batch, s->transB ? s->K : s->N,
                            h->full_rows) == 3;

@@ -368,11 +368,4 @@ gemm_f32_kernel(GemmArgs args) {
   }
 }
 
-// Host-side launcher of one instantiation on a stream.
-template <int BM, int BN, int T, int BK, int TA, int TB>
-hipError_t launch_gemm_f32(const GemmArgs& a, hipStream_t stream) {
-  using Cfg = GemmF32Cfg<BM, BN, T, BK, TA, TB>;
-  return launch_flat<4>(gemm_f32_kernel<BM, BN, T, BK, TA, TB>, a, BM, BN, Cfg::NT, stream);
-}
-
 }  // namespace kt

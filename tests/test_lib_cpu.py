@@ -180,30 +180,31 @@ def test_conv_queries(kt):
 
 
 def test_pipeline_query(kt):
-    """Which BF16 / FP8 pipeline a call takes (host only): LDS DMA when every
+    """Which pipeline a call takes (host only): LDS DMA when every
     row starts on a 16-byte boundary and the contiguous extents are whole
     16-byte chunks, or with whole rows promised, at least one chunk reaching
     within the leading dimension."""
     BF16, FP8 = kt.BF16, kt.FP8E4M3
     h = kt.Handle(-1)
     shp = kt.shape(64, 64, 64)
-    assert h.lp_pipeline_dma(BF16, shp, 0x1000, 64, 0, 0x2000, 64, 0)
-    assert not h.lp_pipeline_dma(0, shp, 0x1000, 64, 0, 0x2000, 64, 0)          # FP32
-    assert not h.lp_pipeline_dma(BF16, shp, 0x1008, 64, 0, 0x2000, 64, 0)       # base
-    assert not h.lp_pipeline_dma(BF16, shp, 0x1000, 68, 0, 0x2000, 64, 0)       # lda
-    assert not h.lp_pipeline_dma(BF16, kt.shape(64, 64, 60), 0x1000, 64, 0, 0x2000, 64, 0)
-    assert not h.lp_pipeline_dma(BF16, kt.shape(64, 60, 64), 0x1000, 64, 0, 0x2000, 64, 0)
-    assert h.lp_pipeline_dma(BF16, kt.shape(60, 64, 64, 1, 0, 1), 0x1000, 64, 0, 0x2000,
+    assert h.dma_pipeline(BF16, shp, 0x1000, 64, 0, 0x2000, 64, 0)
+    assert h.dma_pipeline(0, shp, 0x1000, 64, 0, 0x2000, 64, 0)              # FP32 too
+    assert not h.dma_pipeline(0, shp, 0x1000, 66, 0, 0x2000, 64, 0)          # FP32, odd rows
+    assert not h.dma_pipeline(BF16, shp, 0x1008, 64, 0, 0x2000, 64, 0)       # base
+    assert not h.dma_pipeline(BF16, shp, 0x1000, 68, 0, 0x2000, 64, 0)       # lda
+    assert not h.dma_pipeline(BF16, kt.shape(64, 64, 60), 0x1000, 64, 0, 0x2000, 64, 0)
+    assert not h.dma_pipeline(BF16, kt.shape(64, 60, 64), 0x1000, 64, 0, 0x2000, 64, 0)
+    assert h.dma_pipeline(BF16, kt.shape(60, 64, 64, 1, 0, 1), 0x1000, 64, 0, 0x2000,
                                      64, 0)                                             # M free
-    assert not h.lp_pipeline_dma(FP8, shp, 0x1000, 72, 0, 0x2000, 64, 0)
-    assert not h.lp_pipeline_dma(BF16, kt.shape(64, 64, 64, 2), 0x1000, 64, 4100, 0x2000,
+    assert not h.dma_pipeline(FP8, shp, 0x1000, 72, 0, 0x2000, 64, 0)
+    assert not h.dma_pipeline(BF16, kt.shape(64, 64, 64, 2), 0x1000, 64, 4100, 0x2000,
                                          64, 4096)                                      # stride
     ragged = kt.shape(64, 60, 61)                       # K and N off 16-byte chunks
-    assert not h.lp_pipeline_dma(BF16, ragged, 0x1000, 64, 0, 0x2000, 64, 0)
+    assert not h.dma_pipeline(BF16, ragged, 0x1000, 64, 0, 0x2000, 64, 0)
     h.set_full_rows(True)
-    assert h.lp_pipeline_dma(BF16, ragged, 0x1000, 64, 0, 0x2000, 64, 0)
-    assert not h.lp_pipeline_dma(BF16, ragged, 0x1000, 64, 0, 0x2000, 56, 0)   # ldb short of 64
-    assert not h.lp_pipeline_dma(BF16, kt.shape(64, 60, 5), 0x1000, 8, 0, 0x2000, 64, 0)
+    assert h.dma_pipeline(BF16, ragged, 0x1000, 64, 0, 0x2000, 64, 0)
+    assert not h.dma_pipeline(BF16, ragged, 0x1000, 64, 0, 0x2000, 56, 0)   # ldb short of 64
+    assert not h.dma_pipeline(BF16, kt.shape(64, 60, 5), 0x1000, 8, 0, 0x2000, 64, 0)
     h.set_full_rows(False)
-    assert not h.lp_pipeline_dma(BF16, ragged, 0x1000, 64, 0, 0x2000, 64, 0)
+    assert not h.dma_pipeline(BF16, ragged, 0x1000, 64, 0, 0x2000, 64, 0)
     h.close()

@@ -6,7 +6,7 @@ order, so on the same operands they must agree bit for bit, for every
 configuration and layout, with ragged M and N, a partial last K stage, a
 single partial stage and an empty K.  The register-staged run takes copies
 of the operands placed 4 bytes off a 16-byte boundary, which routes it to
-that pipeline (kt_lp_pipeline tells which one runs).  Every result is also
+that pipeline (kt_dma_pipeline tells which one runs).  Every result is also
 held to the accuracy bar against the FP64 oracle on the dequantized
 operands: the FP32-accumulation bound for BF16 and a relative Frobenius
 error of 1e-3 for FP8 (the FP8 MFMA does not accumulate at full FP32
@@ -72,8 +72,8 @@ def _case(h, torch, kt, dtype, M, N, K, bt, ta, tb, cfgs, seed, beta=0.0):
     ce = 8 if dtype == BF16 else 16      # an empty K keeps 16-byte rows
     lda, ldb = (M if ta else K) or ce, (K if tb else N) or ce
     shp = kt.shape(M, N, K, bt, ta, tb)
-    assert h.lp_pipeline_dma(dtype, shp, qa, lda, M * K, qb, ldb, K * N)
-    assert not h.lp_pipeline_dma(dtype, shp, oa.data_ptr() + 4, lda, M * K,
+    assert h.dma_pipeline(dtype, shp, qa, lda, M * K, qb, ldb, K * N)
+    assert not h.dma_pipeline(dtype, shp, oa.data_ptr() + 4, lda, M * K,
                                  ob.data_ptr() + 4, ldb, K * N)
     c_init = c0 if beta != 0 else np.full_like(c0, np.nan)
     ref = 1.25 * np.einsum("bik,bkj->bij", deq_a, deq_b)
@@ -135,3 +135,54 @@ def test_large_tiles_many_stages(gpu, kt, dtype):
     for ta, tb in synth.LAYOUTS:
         bad = _case(h, torch, kt, dtype, 512, 384, 1024, 1, ta, tb, cfgs, 800 + ta + 2 * tb)
         assert not bad, (ta, tb, bad[:4])
+
+
+def _f32_dma_configs(h):
+    """FP32 configurations with a DMA pipeline: t >= 2, whole-KiB tiles."""
+    return [i for i, (bm, bn, t, bk) in enumerate(h.configs())
+            if t >= 2 and (bm * bk * 4) % 1024 == 0 and (bn * bk * 4) % 1024 == 0]
+
+
+@pytest.mark.parametrize("ta,tb", synth.LAYOUTS)
+@pytest.mark.parametrize("M,N,K,bt,beta", [(200, 136, 172, 2, 0.0), (64, 96, 32, 1, -0.5),
+                                           (132, 68, 1028, 1, 1.0)])
+def test_f32_dma_every_config(gpu, kt, ta, tb, M, N, K, bt, beta):
+    """FP32 through the DMA pipeline (16-byte rows, extents whole 4-float
+    chunks; ragged against the tiles, a partial last K stage) on every
+    configuration that has one, and the register-staged pipeline on operand
+    copies 4 bytes off a 16-byte boundary: both within the FP32 bound
+    1e-5 sqrt(K) |alpha| max|A| max|B| + 2^-23 |beta C0| of the oracle."""
+    from oracle import gemm as og
+    h, torch = gpu
+    a = synth.uniform_operand(synth.operand_seed(950 + M, 0), bt * M * K).reshape(bt, M, K)
+    b = synth.uniform_operand(synth.operand_seed(950 + N, 1), bt * K * N).reshape(bt, K, N)
+    c0 = synth.uniform_operand(synth.operand_seed(950 + K, 2), bt * M * N).reshape(bt, M, N)
+    ref = og.gemm(M, N, K, bt, 0, 0, 1.5, beta, a, K, M * K, b, N, K * N, c0, N, M * N)
+    amax = np.abs(a).reshape(bt, -1).max(axis=1)
+    bmax = np.abs(b).reshape(bt, -1).max(axis=1)
+    tol = (1e-5 * math.sqrt(K) * 1.5 * amax * bmax)[:, None, None] + \
+        2.0 ** -23 * np.abs(beta * c0.astype(np.float64))
+    sa, sb = _stored(a, ta), _stored(b, tb)
+    dA = torch.from_numpy(sa).cuda()
+    dB = torch.from_numpy(sb).cuda()
+    offA = torch.zeros(sa.size + 8, dtype=torch.float32, device="cuda")
+    offB = torch.zeros(sb.size + 8, dtype=torch.float32, device="cuda")
+    offA[1:1 + sa.size] = dA.reshape(-1)
+    offB[1:1 + sb.size] = dB.reshape(-1)
+    lda, ldb = (M if ta else K), (K if tb else N)
+    shp = kt.shape(M, N, K, bt, ta, tb)
+    assert h.dma_pipeline(kt.F32, shp, dA, lda, M * K, dB, ldb, K * N)
+    assert not h.dma_pipeline(kt.F32, shp, offA.data_ptr() + 4, lda, M * K, offB.data_ptr() + 4,
+                              ldb, K * N)
+    init = c0 if beta != 0 else np.full_like(c0, np.nan)
+    bad = []
+    for cid in _f32_dma_configs(h):
+        for (A, B) in ((dA, dB), (offA.data_ptr() + 4, offB.data_ptr() + 4)):
+            dC = torch.from_numpy(init.copy()).cuda()
+            h.gemm_raw(kt.F32, shp, 1.5, A, lda, M * K, B, ldb, K * N, beta, dC, N, M * N,
+                       config_id=cid)
+            torch.cuda.synchronize()
+            got = dC.cpu().numpy()
+            if not np.all(np.abs(got - ref) <= tol):
+                bad.append((cid, h.get_config(cid), A is dA, float(np.nanmax(np.abs(got - ref)))))
+    assert not bad, bad[:6]
