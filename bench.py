@@ -635,7 +635,7 @@ def selection_latency(kt, h, torch, problems, stream, reps=20):
 
 
 def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k, steps, stream,
-                 mws, mws_bytes):
+                 mws, mws_bytes, pad=False):
     """BF16 / FP8 paths on the same 1200 problems: their own sweep tables,
     k-means pruning on the training shapes, decision trees A/B/C and the MLP
     scored on the held-out shapes, the selector chosen on validation shapes
@@ -656,7 +656,8 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
             continue
         TL, PL, CL, metaL = tune.load_table(path)
         if not (TL >= 0).all() or [tuple(int(v) for v in p) for p in PL] != problems or \
-                [tuple(c) for c in CL.tolist()] != h.kernels(dt)[:len(CL)]:
+                [tuple(c) for c in CL.tolist()] != h.kernels(dt)[:len(CL)] or \
+                bool(metaL.get("pad_rows", False)) != pad:
             continue
         tl = TL.min(axis=1).astype(np.float64)
         ws_bytes = kt.Handle.prune_workspace_bytes(len(tr_rows), TL.shape[1], k, 10)
@@ -1103,11 +1104,16 @@ def main(argv=None):
     pool = torch.empty(ws_all // 4 + 64, dtype=torch.float32, device="cuda")
     h.fill_uniform(pool, pool.numel(), synth.operand_seed(synth.SEED, 0), stream=stream)
     base = pool.data_ptr()
+    # the operand layout the table was measured with: rows padded to 16
+    # elements (allocated in full, promised to the library) or dense
+    pad = bool(meta.get("pad_rows", False))
+    h.set_full_rows(pad)
+    rnd = (lambda v: (v + 15) // 16 * 16) if pad else (lambda v: v)
     plans = []
     for (M, N, K, b, ta, tb) in problems:
-        lda = M if ta else K
-        ldb = K if tb else N
-        sA, sB, sC = M * K, K * N, M * N
+        lda = rnd(M if ta else K)
+        ldb = rnd(K if tb else N)
+        sA, sB, sC = (K if ta else M) * lda, (N if tb else K) * ldb, M * N
         offB = ((b * sA * 4 + 255) // 256) * 256
         offC = offB + ((b * sB * 4 + 255) // 256) * 256
         plans.append((kt.shape(M, N, K, b, ta, tb), base, lda, sA, base + offB, ldb, sB,
@@ -1220,6 +1226,7 @@ def main(argv=None):
             "algorithmic_bytes_per_launch": int(dom_bytes / len(dom_rows)),
             "kernel_ms_per_step": round(dom_ms, 3),
         },
+        "operand_rows": "padded to 16 elements" if pad else "dense",
         "table": {"path": os.path.relpath(table_path, ROOT), "device": meta.get("device"),
                   "sweep_seconds": round(meta.get("seconds", 0.0), 1)},
         "deploy": deploy_info(chosen, [h.num_configs(d) for d in (kt.F32, kt.BF16, kt.FP8E4M3)]),
@@ -1234,7 +1241,7 @@ def main(argv=None):
         out["conv_heldout"] = conv
     if not a.no_lowp:
         lp = lowp_section(kt, h, torch, tune, synth, problems, T, pool, plans, flops, k, 3, stream,
-                          mws, mws_bytes)
+                          mws, mws_bytes, pad=pad)
         if lp:
             out["lowp"] = lp
             _log(f"bench: low precision {json.dumps(lp)}")

@@ -348,11 +348,15 @@ typedef struct {
   float pause_ms;       /* host sleep between rows, to limit heating */
   uint64_t seed;        /* operand seed base: A, B (and C if beta != 0) are filled per row */
   float alpha, beta;
+  int32_t pad_rows;     /* 1: rows of A and B padded to a multiple of 16 elements (leading
+                           dimension rounded up, rows allocated in full: 16-byte rows in
+                           every dtype); 0: dense rows */
 } kt_sweep_opts;
 
 /* Device workspace needed to sweep these shapes with any kernels: operands
- * of the largest shape, 256-byte aligned, plus the largest partial planes
- * any split-K variant of the dtype takes on it. */
+ * of the largest shape (rows padded to 16 elements, which also covers dense
+ * rows), 256-byte aligned, plus the largest partial planes any split-K
+ * variant of the dtype takes on it. */
 kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_dtype dtype,
                                    size_t* bytes);
 /* Time every (shape, kernel) pair (sections 3 and 3.1): for each shape the

@@ -43,7 +43,7 @@ class Config(ctypes.Structure):
 class SweepOpts(ctypes.Structure):
     _fields_ = [("warmup", c_i32), ("target_ms", c_f32), ("min_reps", c_i32), ("max_reps", c_i32),
                 ("cut_factor", c_f32), ("pause_ms", c_f32), ("seed", c_u64),
-                ("alpha", c_f32), ("beta", c_f32)]
+                ("alpha", c_f32), ("beta", c_f32), ("pad_rows", c_i32)]
 
 
 class MlpOpts(ctypes.Structure):
@@ -475,7 +475,7 @@ class Handle:
 
     def sweep(self, shapes, workspace, ws_bytes, config_ids=None, time_ns=None, warmup=1,
               target_ms=2.0, min_reps=3, max_reps=200, cut_factor=8.0, pause_ms=0.0, seed=13145,
-              alpha=1.0, beta=0.0, dtype=F32, stream=None):
+              alpha=1.0, beta=0.0, dtype=F32, stream=None, pad_rows=False):
         arr = shapes_array(shapes)
         n_cfg = self.num_kernels(dtype) if config_ids is None else len(config_ids)
         if time_ns is None:
@@ -486,7 +486,7 @@ class Handle:
         if config_ids is not None:
             ids = np.ascontiguousarray(config_ids, dtype=np.int32)
         opts = SweepOpts(warmup, target_ms, min_reps, max_reps, cut_factor, pause_ms,
-                         int(seed) & (2 ** 64 - 1), alpha, beta)
+                         int(seed) & (2 ** 64 - 1), alpha, beta, 1 if pad_rows else 0)
         self._check(self.L.kt_sweep(self.h, dtype, arr, len(shapes),
                                     None if ids is None else ids.ctypes.data, n_cfg,
                                     ctypes.byref(opts), _ptr(workspace), int(ws_bytes),

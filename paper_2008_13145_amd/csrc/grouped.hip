@@ -45,27 +45,36 @@ struct WorkItem {
   int32_t g, tm, tn, cls;   // cls 0: the large tile, 1: the small tile
 };
 
-template <int BM, int BN, int T, int BK>
+// One tile class.  WITH_DMA: members whose operands allow it take the DMA
+// pipeline (the kernel then reserves its LDS); without, every member is
+// register-staged and the kernel keeps the smaller LDS footprint (more
+// resident work-groups) -- the plan picks the variant by its members.
+template <int BM, int BN, int T, int BK, bool WITH_DMA>
 struct GroupTile {
   static constexpr int NT = BM * BN / (T * T);
   static constexpr int L1 = GemmLpCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES;
-  static constexpr int L2 = LpDmaCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES;
+  static constexpr int L2 = WITH_DMA ? LpDmaCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES : 0;
   static constexpr int LDS = L1 > L2 ? L1 : L2;
 
   __device__ __forceinline__ static void run(const GemmArgs& a, int tm, int tn, bool dma,
                                              char* lds) {
-    if (dma) lp_dma_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, lds);
-    else lp_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, reinterpret_cast<uint16_t*>(lds));
+    if constexpr (WITH_DMA) {
+      if (dma) {
+        lp_dma_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, lds);
+        return;
+      }
+    }
+    lp_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, reinterpret_cast<uint16_t*>(lds));
   }
 };
 
-template <int BM, int BN, int T, int BK, int SM, int SN, int ST, int SK>
+template <int BM, int BN, int T, int BK, int SM, int SN, int ST, int SK, bool WITH_DMA>
 __global__ void __launch_bounds__(BM * BN / (T * T))
 grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restrict__ work,
                     int32_t n_work, float alpha, float beta, int32_t dynamic,
                     uint32_t* __restrict__ counter, uint32_t* __restrict__ visits) {
-  using Big = GroupTile<BM, BN, T, BK>;
-  using Small = GroupTile<SM, SN, ST, SK>;
+  using Big = GroupTile<BM, BN, T, BK, WITH_DMA>;
+  using Small = GroupTile<SM, SN, ST, SK, WITH_DMA>;
   static_assert(Big::NT == Small::NT, "both tiles of a grouped kernel have the same waves");
   constexpr int LDS = Big::LDS > Small::LDS ? Big::LDS : Small::LDS;
   __shared__ __attribute__((aligned(16))) char lds[LDS];
@@ -105,10 +114,13 @@ typedef void (*GroupedKernel)(const GroupDesc*, const WorkItem*, int32_t, float,
 struct GroupedVariant {
   int bm, bn, t, bk;       // large tile
   int sm, sn, st, sk;      // small tile (same waves)
-  GroupedKernel fn;
+  GroupedKernel fn_reg;    // every member register-staged
+  GroupedKernel fn_dma;    // members with 16-byte rows through LDS DMA
 };
 
-#define KT_GV(a, b, c, d, e, f, g, h) {a, b, c, d, e, f, g, h, grouped_bf16_kernel<a, b, c, d, e, f, g, h>}
+#define KT_GV(a, b, c, d, e, f, g, h)                                            \
+  {a, b, c, d, e, f, g, h, grouped_bf16_kernel<a, b, c, d, e, f, g, h, false>, \
+   grouped_bf16_kernel<a, b, c, d, e, f, g, h, true>}
 // Tile pairs the grouped kernel is compiled for (members of the BF16
 // configuration space).
 static const GroupedVariant kGroupedVariants[] = {
@@ -259,7 +271,10 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess && n_work > 0) {
     if (o.schedule == 1) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, cs, d_counter);
-    hipLaunchKernelGGL(v->fn, dim3(grid), dim3(threads), 0, cs, (const GroupDesc*)d_desc,
+    bool any_dma = false;
+    for (const GroupDesc& d : descs) any_dma = any_dma || d.dma;
+    hipLaunchKernelGGL(any_dma ? v->fn_dma : v->fn_reg, dim3(grid), dim3(threads), 0, cs,
+                       (const GroupDesc*)d_desc,
                        (const WorkItem*)d_work, n_work, alpha, beta, (int32_t)o.schedule, d_counter,
                        o.visits);
   }

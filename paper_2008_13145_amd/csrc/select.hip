@@ -208,7 +208,13 @@ static kt_status time_candidates(Ctx* h, int dtype, const kt_shape* s,
   const int64_t eb = elem_bytes_sel(dtype);
   const int64_t a_rows = s->transA ? s->K : s->M, a_cols = s->transA ? s->M : s->K;
   const int64_t b_rows = s->transB ? s->N : s->K, b_cols = s->transB ? s->K : s->N;
-  const int64_t lda = std::max<int64_t>(a_cols, 1), ldb = std::max<int64_t>(b_cols, 1);
+  // rows padded to 16 elements when the caller promises whole rows (the
+  // sweep's padded layout), else dense
+  auto ld_of = [&](int64_t cols) {
+    const int64_t c = std::max<int64_t>(cols, 1);
+    return h->full_rows ? (c + 15) / 16 * 16 : c;
+  };
+  const int64_t lda = ld_of(a_cols), ldb = ld_of(b_cols);
   const int64_t ldc = std::max<int64_t>(s->N, 1);
   const int64_t nA = s->batch * a_rows * lda, nB = s->batch * b_rows * ldb, nC = s->batch * s->M * ldc;
   auto r256 = [](int64_t b) { return (b + 255) & ~(int64_t)255; };

@@ -25,16 +25,23 @@ struct OperandPlan {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Dense operands of one problem, packed in a workspace: A, B (element type of
-// the dtype), C (FP32), then for BF16 / FP8 an FP32 staging area the operands
-// are generated in before conversion, and two FP8 scales plus the amax slot.
-static OperandPlan plan_for(const kt_shape& s, int dtype) {
+// Operands of one problem, packed in a workspace: A, B (element type of the
+// dtype), C (FP32), then for BF16 / FP8 an FP32 staging area the operands are
+// generated in before conversion, and two FP8 scales plus the amax slot.
+// Rows of A and B are dense, or with pad_rows rounded up to a multiple of 16
+// elements (allocated in full), which puts every row on a 16-byte boundary
+// in every dtype and keeps one layout for all of them.
+static OperandPlan plan_for(const kt_shape& s, int dtype, bool pad_rows) {
   OperandPlan p;
   const int64_t eb = elem_bytes_of(dtype);
   const int64_t a_rows = s.transA ? s.K : s.M, a_cols = s.transA ? s.M : s.K;
   const int64_t b_rows = s.transB ? s.N : s.K, b_cols = s.transB ? s.K : s.N;
-  p.lda = std::max<int64_t>(a_cols, 1);
-  p.ldb = std::max<int64_t>(b_cols, 1);
+  auto ld_of = [&](int64_t cols) {
+    const int64_t c = std::max<int64_t>(cols, 1);
+    return pad_rows ? (c + 15) / 16 * 16 : c;
+  };
+  p.lda = ld_of(a_cols);
+  p.ldb = ld_of(b_cols);
   p.ldc = std::max<int64_t>(s.N, 1);
   p.sA = a_rows * p.lda;
   p.sB = b_rows * p.ldb;
@@ -99,7 +106,8 @@ kt_status kt_sweep_workspace_bytes(const kt_shape* shapes, int32_t n_shapes, kt_
   size_t m = 0;
   for (int32_t i = 0; i < n_shapes; ++i) {
     if (shapes[i].M < 0 || shapes[i].N < 0 || shapes[i].K < 0 || shapes[i].batch < 0) return KT_EINVAL;
-    m = std::max(m, plan_for(shapes[i], dtype).total + max_split_planes(dtype, shapes[i]));
+    // the padded layout bounds the dense one
+    m = std::max(m, plan_for(shapes[i], dtype, true).total + max_split_planes(dtype, shapes[i]));
   }
   *bytes = m;
   return KT_OK;
@@ -125,8 +133,10 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
   }
   for (int32_t id : ids)
     if (!valid_kernel(h, dtype, id)) return fail(h, KT_EINVAL, "kernel id out of range");
-  if (opts->min_reps < 1 || opts->max_reps < opts->min_reps || opts->warmup < 0 || opts->target_ms < 0)
+  if (opts->min_reps < 1 || opts->max_reps < opts->min_reps || opts->warmup < 0 ||
+      opts->target_ms < 0 || (opts->pad_rows & ~1))
     return fail(h, KT_EINVAL, "bad sweep options");
+
   hipStream_t stream = (hipStream_t)stream_v;
   // Visit large work-group tiles first so the early cut has a tight
   // reference; split-K variants after every configuration.
@@ -147,13 +157,16 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
   he = hipEventCreate(&e1);
   if (he != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(h, he, "hipEventCreate"); }
   kt_status result = KT_OK;
+  // padded rows are allocated in full, which the DMA pipelines may rely on
+  const bool keep_full_rows = h->full_rows;
+  if (opts->pad_rows) h->full_rows = true;
   for (int32_t r = 0; r < n_shapes && result == KT_OK; ++r) {
     const kt_shape& s = shapes[r];
     int64_t* row = time_ns + (int64_t)r * n_configs;
     bool done = true;
     for (int32_t c = 0; c < n_configs; ++c) done = done && row[c] >= 0;
     if (done) continue;
-    OperandPlan p = plan_for(s, dtype);
+    OperandPlan p = plan_for(s, dtype, opts->pad_rows != 0);
     size_t planes = 0;   // partial planes of the split-K kernels in the list
     for (int32_t id : ids) planes = std::max(planes, kernel_plane_bytes(h, dtype, &s, id));
     if (!workspace || ws_bytes < p.total + planes) {
@@ -213,6 +226,7 @@ kt_status kt_sweep(kt_handle hh, kt_dtype dtype, const kt_shape* shapes, int32_t
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  h->full_rows = keep_full_rows;
   return result;
 }
 

@@ -126,7 +126,8 @@ def save_table(path, time_ns, problems, configs, meta):
 
 
 def run_sweep(out, budget_s=900.0, target_ms=5.0, min_reps=3, max_reps=200,
-              cut_factor=8.0, warmup=2, limit=None, log=print, dtype=0, set_name="sweep"):
+              cut_factor=8.0, warmup=2, limit=None, log=print, dtype=0, set_name="sweep",
+              pad_rows=True):
     import torch
 
     import synth
@@ -140,21 +141,25 @@ def run_sweep(out, budget_s=900.0, target_ms=5.0, min_reps=3, max_reps=200,
         T, P, C, meta = load_table(out)
         if P.tolist() != [list(p) for p in problems] or C.tolist() != [list(c) for c in configs]:
             raise RuntimeError(f"{out} was made for another problem set or configuration space")
+        if bool(meta.get("pad_rows", False)) != pad_rows:
+            raise RuntimeError(f"{out} was measured with another operand layout")
     else:
         T = np.full((len(problems), len(configs)), -1, np.int64)
         props = torch.cuda.get_device_properties(0)
         meta = dict(device=props.name, arch=getattr(props, "gcnArchName", ""),
                     opts=dict(target_ms=target_ms, min_reps=min_reps, max_reps=max_reps,
                               cut_factor=cut_factor, warmup=warmup),
-                    seed=synth.SEED, started=time.time(), seconds=0.0, dtype=dtype)
+                    seed=synth.SEED, started=time.time(), seconds=0.0, dtype=dtype,
+                    pad_rows=bool(pad_rows))
     ws_bytes = Handle.sweep_workspace_bytes(problems, dtype)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     # Load every kernel once on a tiny problem, so that no row pays for code
     # object loading and the first timed launch of a pair is representative.
-    tiny = [(8, 8, 8, 1, ta, tb) for (ta, tb) in synth.LAYOUTS]
-    h.sweep(tiny, ws, ws_bytes, warmup=0, target_ms=0.0, min_reps=1, max_reps=1, cut_factor=0.0,
-            dtype=dtype)
+    tiny = [(16, 16, 16, 1, ta, tb) for (ta, tb) in synth.LAYOUTS]
+    for pad in (False, True):     # both pipelines of every kernel
+        h.sweep(tiny, ws, ws_bytes, warmup=0, target_ms=0.0, min_reps=1, max_reps=1,
+                cut_factor=0.0, dtype=dtype, pad_rows=pad)
     t0 = time.time()
     last_save = time.time()
     todo = [i for i in range(len(problems)) if (T[i] < 0).any()]
@@ -166,7 +171,8 @@ def run_sweep(out, budget_s=900.0, target_ms=5.0, min_reps=3, max_reps=200,
         sub = T[i:i + 1].copy()
         ts = time.time()
         h.sweep([problems[i]], ws, ws_bytes, time_ns=sub, warmup=warmup, target_ms=target_ms,
-                min_reps=min_reps, max_reps=max_reps, cut_factor=cut_factor, dtype=dtype)
+                min_reps=min_reps, max_reps=max_reps, cut_factor=cut_factor, dtype=dtype,
+                pad_rows=pad_rows)
         T[i] = sub[0]
         meta["seconds"] = meta.get("seconds", 0.0) + (time.time() - ts)
         if time.time() - last_save > 20 or n_done == len(todo) - 1:
@@ -192,6 +198,8 @@ def main(argv=None):
     s.add_argument("--out", default=None)
     s.add_argument("--budget-s", type=float, default=900.0)
     s.add_argument("--limit", type=int, default=None)
+    s.add_argument("--dense-rows", action="store_true",
+                   help="operands with dense rows (default: rows padded to 16 bytes)")
     d = sub.add_parser("deploy")
     d.add_argument("--table", default=DEFAULT_TABLE)
     d.add_argument("--k", type=int, default=8)
@@ -201,7 +209,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "sweep":
         run_sweep(a.out or table_path(a.dtype, a.set), a.budget_s, limit=a.limit,
-                  dtype=DTYPE_NAMES[a.dtype], set_name=a.set)
+                  dtype=DTYPE_NAMES[a.dtype], set_name=a.set, pad_rows=not a.dense_rows)
     elif a.cmd == "deploy":
         # choose the k kernels by GPU k-means over the training problems of the
         # measured table, record them, and build the library with only those

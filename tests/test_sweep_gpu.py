@@ -51,3 +51,21 @@ def test_sweep_workspace_checked(gpu):
     with pytest.raises(kt.KtError) as e:
         h.sweep(problems, ws, 1024, config_ids=[0])
     assert e.value.status == -5
+
+
+def test_sweep_padded_rows(gpu):
+    """Rows padded to 16 elements: every pair timed (the DMA pipelines run
+    with the whole-rows promise the sweep makes for its own operands), and
+    the handle's own whole-rows setting is left as it was."""
+    import paper_2008_13145_amd as kt
+    h, torch = gpu
+    problems = [(100, 36, 77, 2, 0, 0), (33, 130, 45, 1, 1, 1)]
+    ids = [0, 60, 112, 130]
+    ws_bytes = kt.Handle.sweep_workspace_bytes(problems)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    for dt in (kt.F32, kt.BF16):
+        T = h.sweep(problems, ws, ws_bytes, config_ids=ids, target_ms=0.2, max_reps=10,
+                    pad_rows=True, dtype=dt)
+        assert (T > 0).all()
+    shp = kt.shape(64, 60, 61)
+    assert not h.dma_pipeline(kt.BF16, shp, 0x1000, 64, 0, 0x2000, 64, 0)
