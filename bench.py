@@ -109,7 +109,8 @@ def measured_traffic(kernel_name):
     kernel source has not changed since the counters were taken; else None."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_2008_13145_amd", "csrc", "gemm_f32.hpp")
+    hdr = "gemm_f32_dma.hpp" if kernel_name.startswith("gemm_f32_dma_kernel") else "gemm_f32.hpp"
+    src = os.path.join(ROOT, "paper_2008_13145_amd", "csrc", hdr)
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt"))):
         fields = {}
@@ -871,6 +872,9 @@ def main(argv=None):
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16/FP8 sections")
     ap.add_argument("--calibrate-counters", action="store_true",
                     help="only run the known-traffic conversion kernel (HBM counter scaling)")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only pruning, the deployed selector and the timed steps (for counter "
+                         "runs: the dominant kernel's last dispatches are the timed step's)")
     ap.add_argument("--square-only", action="store_true",
                     help="only the BF16 / FP8 4096^3 section (for profiling its kernels)")
     a = ap.parse_args(argv)
@@ -964,17 +968,19 @@ def main(argv=None):
     mws_bytes = kt.Handle.mlp_workspace_bytes(len(tr_rows), n_cfg, max(k, 15))
     mws = torch.empty(mws_bytes, dtype=torch.uint8, device="cuda")
     h.set_fallback(0)
-    for kind in (0, 1, 2, 3):
+    for kind in (() if a.step_only else (0, 1, 2, 3)):
         t0 = time.perf_counter()
         h.fit_selector(kind, tr_shapes, T[tr_rows], chosen, mlp_steps=3000, mlp_graph_steps=25,
                        workspace=mws, ws_bytes=mws_bytes, stream=stream)
         torch.cuda.synchronize()
         fit_ms[SEL_NAMES[kind]] = (time.perf_counter() - t0) * 1e3
         record(SEL_NAMES[kind], ev_picks([h.select(*problems[r]) for r in te_rows]))
-    infer_mlp = selection_latency(kt, h, torch, problems, stream)    # h holds the MLP here
+    infer_mlp = None if a.step_only else \
+        selection_latency(kt, h, torch, problems, stream)    # h holds the MLP here
     h.set_fallback(1)
-    conv = conv_section(kt, h, tune, tune.table_path("f32", "conv"), (0, 1, 2, 3),
-                        (tr_shapes, T[tr_rows], chosen, mws, mws_bytes, stream))
+    conv = None if a.step_only else \
+        conv_section(kt, h, tune, tune.table_path("f32", "conv"), (0, 1, 2, 3),
+                     (tr_shapes, T[tr_rows], chosen, mws, mws_bytes, stream))
 
     # ---- the paper's comparison over the number of deployed kernels: for
     # each k, pruning (normalization chosen on the training rows), Top-N and
@@ -983,7 +989,7 @@ def main(argv=None):
     k_sweep = {}
     hk = kt.Handle(0)
     hk.set_fallback(0)
-    for kk in (4, 5, 6, 8, 15):
+    for kk in (() if a.step_only else (4, 5, 6, 8, 15)):
         s_k = tune.select_pruning(hk, T[tr_rows], kk, synth.SEED, workspace=pws,
                                   ws_bytes=ws_bytes, stream=stream)
         tn_k = hk.prune_topn(T[tr_rows], kk, workspace=pws, ws_bytes=ws_bytes, stream=stream)
@@ -1003,7 +1009,7 @@ def main(argv=None):
     # rows of the full table
     sparse = {}
     rng_s = np.random.default_rng(synth.SEED + 7)
-    for frac in (0.05, 0.1, 0.25, 0.5, 1.0):
+    for frac in (() if a.step_only else (0.05, 0.1, 0.25, 0.5, 1.0)):
         T_s = T[tr_rows].copy()
         T_s[rng_s.random(T_s.shape) >= frac] = -1
         ch_s = hk.prune(T_s, k, norm=sel["norm"], seed=synth.SEED, n_init=10, max_iter=300,
@@ -1013,7 +1019,7 @@ def main(argv=None):
     # training table, then the same k-means; each centroid read back through
     # the components (the paper's representative rule)
     pca = {}
-    for dims in (8, 16, 32):
+    for dims in (() if a.step_only else (8, 16, 32)):
         r_p = tune.pca_pruning(hk, T[tr_rows], k, synth.SEED, dims, sel["norm"], workspace=pws,
                                ws_bytes=ws_bytes, stream=stream)
         pca[str(dims)] = {"explained_variance": round(r_p["explained"], 4),
@@ -1025,7 +1031,7 @@ def main(argv=None):
     def ceil_test(ch):
         return round(100 * ev_ceiling(ch)["geomean"], 2)
     grid = {"top_n": ceil_test(topn)}
-    for norm, name in enumerate(tune.NORM_NAMES):
+    for norm, name in enumerate(() if a.step_only else tune.NORM_NAMES):
         cell = {}
         for rep, rname in ((0, "centroid"), (1, "geomean_of_members")):
             cell[f"kmeans_{rname}"] = ceil_test(tune.kmeans_pruning(
@@ -1097,7 +1103,8 @@ def main(argv=None):
             h.select(*p)
     select_us = (time.perf_counter() - t0) / (5 * n_prob) * 1e6
     sel_all = ev_picks(picks_all, list(range(n_prob)))
-    infer = {"deployed": selection_latency(kt, h, torch, problems, stream), "MLP": infer_mlp}
+    infer = None if a.step_only else \
+        {"deployed": selection_latency(kt, h, torch, problems, stream), "MLP": infer_mlp}
 
     # ---- operands resident in HBM: one pool sized for the largest problem
     ws_all = kt.Handle.sweep_workspace_bytes(problems)
@@ -1167,7 +1174,10 @@ def main(argv=None):
     dom_ms = float(t_launch[dom_rows].sum())
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     bm, bn, tt, bk = cfgs[dom[0]][:4]
-    dom_name = f"gemm_f32_kernel<{bm}, {bn}, {tt}, {bk}, {dom[1]}, {dom[2]}>"
+    # padded rows put every operand on the LDS-DMA pipeline where the
+    # configuration has one (t >= 2, tiles of whole KiB)
+    dma = pad and tt >= 2 and (bm * bk * 4) % 1024 == 0 and (bn * bk * 4) % 1024 == 0
+    dom_name = f"gemm_f32{'_dma' if dma else ''}_kernel<{bm}, {bn}, {tt}, {bk}, {dom[1]}, {dom[2]}>"
 
     # exhaustive-best comparison: live launch times vs the table's best
     t_best = T.min(axis=1).astype(np.float64)
@@ -1237,6 +1247,15 @@ def main(argv=None):
         "gpu_state": {"before": state_before, "after": state_after},
     }
     _log(f"bench: {value:.2f} TFLOP/s, {ms_per_step:.1f} ms/step")
+    if a.step_only:
+        # the dominant configuration's problems in each layout, in launch order
+        out["dominant_config_problems"] = {
+            f"{ta}{tb}": [list(problems[i]) for i in range(n_prob)
+                          if picks_all[i] == dom[0] and problems[i][4:6] == (ta, tb)]
+            for ta in (0, 1) for tb in (0, 1)}
+        h.close()
+        print(json.dumps(out), flush=True)
+        return 0
     if conv:
         out["conv_heldout"] = conv
     if not a.no_lowp:

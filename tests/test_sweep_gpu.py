@@ -60,10 +60,11 @@ def test_sweep_padded_rows(gpu):
     import paper_2008_13145_amd as kt
     h, torch = gpu
     problems = [(100, 36, 77, 2, 0, 0), (33, 130, 45, 1, 1, 1)]
-    ids = [0, 60, 112, 130]
     ws_bytes = kt.Handle.sweep_workspace_bytes(problems)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     for dt in (kt.F32, kt.BF16):
+        n = h.num_kernels(dt)       # plain configurations, then split-K variants
+        ids = [0, 60, n - 17, n - 1]
         T = h.sweep(problems, ws, ws_bytes, config_ids=ids, target_ms=0.2, max_reps=10,
                     pad_rows=True, dtype=dt)
         assert (T > 0).all()
