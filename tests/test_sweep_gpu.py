@@ -60,7 +60,7 @@ def test_sweep_padded_rows(gpu):
     import paper_2008_13145_amd as kt
     h, torch = gpu
     problems = [(100, 36, 77, 2, 0, 0), (33, 130, 45, 1, 1, 1)]
-    ws_bytes = kt.Handle.sweep_workspace_bytes(problems)
+    ws_bytes = max(kt.Handle.sweep_workspace_bytes(problems, dt) for dt in (kt.F32, kt.BF16))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     for dt in (kt.F32, kt.BF16):
         n = h.num_kernels(dt)       # plain configurations, then split-K variants
