@@ -735,7 +735,8 @@ def lowp_section(kt, h, torch, tune, synth, problems, T32, pool, plans, flops, k
             "chosen": [list(h.get_kernel(c, dt)[0]) for c in chosen],
             "normalization": sel["norm_name"], "train_ceiling_by_normalization": sel["train_ceiling"],
             "accuracy_bound_rel_frobenius": 1e-2 if dt == kt.BF16 else 4e-2,
-            "roofline": {"bound": "mfma", "kernel": f"gemm_lp_kernel<{eb}, {bm}, {bn}, {tt}, {bk}, "
+            "roofline": {"bound": "mfma", "kernel": f"gemm_lp{'_dma' if pad else ''}_kernel<{eb}, "
+                                                    f"{bm}, {bn}, {tt}, {bk}, "
                                                     f"{dom[1]}, {dom[2]}>",
                          "launches_per_step": len(dom_rows), "achieved": round(dom_tf, 2),
                          "peak": peak, "unit": "TFLOP/s", "frac": round(dom_tf / peak, 4),
