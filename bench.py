@@ -253,7 +253,9 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
     the rest) and the deployed selector's kernel for every GEMM (config -1;
     a selected split-K kernel runs split -- the fully connected layers, M = 1,
     lie outside the training shapes and go to the fallback, which times the
-    chosen kernels and their split-K variants once).  The exhaustive
+    chosen kernels and their split-K variants once; the same inference with
+    the exhaustive fallback, every kernel of the library timed once per
+    out-of-range shape, is reported beside it).  The exhaustive
     reference takes, per layer, the fastest of every lowering x every
     configuration (x split counts 2..32 for the fully connected layers).
     Also reported: the best lowering per layer among the selector's options
@@ -376,6 +378,16 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
                        "ms": round(timed(lambda: h.conv2d(algo_r, cs, xin, wt_of(li, algo_r), biases[li],
                                                           True, out, ws, ws_bytes, stream=stream),
                                          reps), 4)}
+        box = h.selector_info()
+        if any(not (box["box_lo"][f] <= g_shape[f] <= box["box_hi"][f]) for f in range(4)):
+            # outside the training shapes: the exhaustive fallback instead
+            h.set_fallback(2)
+            pick2 = h.select(*g_shape)
+            row["rule_exhaustive_fallback"] = {
+                "selected_kernel": list(h.get_kernel(pick2)[0]),
+                "ms": round(timed(lambda: h.conv2d(algo_r, cs, xin, wt_of(li, algo_r), biases[li],
+                                                   True, out, ws, ws_bytes, stream=stream), reps), 4)}
+            h.set_fallback(1)
         rule_choice.append((algo_r, -1, 1))
         per.append(row)
     ms = {
@@ -386,6 +398,9 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
                                                      -1, 1) for cs in convs]), reps),
         "timed_lowering_selector_kernels": timed(lambda: forward(sel_choice), reps),
     }
+    h.set_fallback(2)
+    ms["selector_exhaustive_fallback"] = timed(lambda: forward(rule_choice), reps)
+    h.set_fallback(1)
     # the selector's inference captured once in a graph and replayed
     out_eager = forward(rule_choice).clone()
     torch.cuda.synchronize()
@@ -405,6 +420,9 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
             "tflops_effective_selector": round(flops / (ms["selector"] * 1e-3) / 1e12, 2),
             "selector_pct_of_exhaustive": round(100 * ms["exhaustive"] / ms["selector"], 2),
             "fc1_selector_vs_exhaustive": round(fc[0]["rule"]["ms"] / fc[0]["im2col"]["ms_exhaustive"], 3),
+            "fc1_selector_exhaustive_fallback_vs_exhaustive": round(
+                fc[0]["rule_exhaustive_fallback"]["ms"] / fc[0]["im2col"]["ms_exhaustive"], 3)
+            if "rule_exhaustive_fallback" in fc[0] else None,
             "exhaustive_choice": [[names[a], list(cfgs[c]), sp] for a, c, sp in ex_choice],
             "timed_lowering_choice": [[names[a], sp] for a, _, sp in sel_choice],
             "graph_replay_matches_eager": graph_ok,
@@ -588,7 +606,8 @@ def grouped_section(kt, h, torch, synth, stream, reps=20):
             "tile": [bm, bn, tt, bk],
             "small_tile": list(h.get_config(best[1], kt.BF16)) if best[1] >= 0 else None,
             "small_max_area": best[2], "schedule": best[3], "order": best[4],
-            "wgs_per_cu": best[5], "work_items": n_work,
+            "wgs_per_cu": best[5], "pipeline": "register-staged" if best[6] else "LDS DMA where the rows allow",
+            "work_items": n_work,
             "autotune_evaluations": evals, "autotune_s": round(tune_s, 3),
             "ms_per_launch": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
             "roofline": {"bound": "per-member max(MFMA at 2.5 PF/s, HBM at 8 TB/s), summed",

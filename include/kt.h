@@ -603,8 +603,12 @@ kt_status kt_fit_selector_validated(kt_handle h, kt_dtype dtype, const kt_shape*
  * shape.  Entry points that must not allocate keep the model's pick. */
 kt_status kt_select(kt_handle h, kt_dtype dtype, const kt_shape* s, int32_t* config_id);
 
-/* Turn the out-of-range fallback of kt_select on (1) or off (0) for the
- * selector of a dtype (kept across refits; saved by kt_save). */
+/* The out-of-range fallback of kt_select for the selector of a dtype (kept
+ * across refits; saved by kt_save): 0 off (the model's pick stands), 1 (the
+ * default) the chosen kernels and the split-K variants of their
+ * configurations -- the code a deployed library holds --, 2 exhaustive:
+ * every kernel this library holds (kt_num_kernels), timed once per shape and
+ * cached like the exhaustive selector.  KT_EINVAL for another value. */
 kt_status kt_set_fallback(kt_handle h, kt_dtype dtype, int32_t enabled);
 
 /* The fitted selector of a dtype (host outputs, each optional): *kind
@@ -654,6 +658,9 @@ typedef struct {
   int32_t schedule;         /* 0: static round robin over work-groups; 1: atomic work counter */
   int32_t order;            /* 0: members in the given order; 1: largest K first */
   int32_t wgs_per_cu;       /* persistent work-groups per compute unit (1..4) */
+  int32_t pipeline;         /* 0: members that allow it take the LDS-DMA pipeline (the kernel
+                               then reserves its LDS); 1: every member register-staged (the
+                               smaller LDS footprint keeps more work-groups resident) */
   uint32_t* visits;         /* optional device counters [n_work]: each work item adds 1 (tests) */
 } kt_grouped_opts;
 
@@ -684,7 +691,8 @@ kt_status kt_grouped_gemm(kt_handle h, kt_dtype dtype, const kt_shape* shapes, i
                           const int64_t* ld, float alpha, float beta, const kt_grouped_opts* opts,
                           void* workspace, size_t ws_bytes, void* stream);
 /* The library's autotuner: successive halving over (tile pair, small-member
- * area in {0, 128^2, 256^2, 512^2}, schedule, order, work-groups per CU),
+ * area in {0, 128^2, 256^2, 512^2}, schedule, order, work-groups per CU,
+ * pipeline -- DMA only when some member allows it),
  * timing whole graph launches of the real group (C is overwritten with
  * alpha = 1, beta = 0).  The winner is returned and kept on the handle as the
  * default for later plans. */

@@ -58,7 +58,8 @@ class Eval(ctypes.Structure):
 
 class GroupedOpts(ctypes.Structure):
     _fields_ = [("config_id", c_i32), ("small_config_id", c_i32), ("small_max_area", c_i64),
-                ("schedule", c_i32), ("order", c_i32), ("wgs_per_cu", c_i32), ("visits", c_vp)]
+                ("schedule", c_i32), ("order", c_i32), ("wgs_per_cu", c_i32), ("pipeline", c_i32),
+                ("visits", c_vp)]
 
 
 class ConvShape(ctypes.Structure):
@@ -689,8 +690,9 @@ class Handle:
             ctypes.byref(kind), scores.ctypes.data))
         return kind.value, scores.tolist()
 
-    def set_fallback(self, enabled, dtype=F32):
-        self._check(self.L.kt_set_fallback(self.h, int(dtype), int(bool(enabled))))
+    def set_fallback(self, mode, dtype=F32):
+        """0 off, 1 (True) the deployed kernels, 2 exhaustive over the library."""
+        self._check(self.L.kt_set_fallback(self.h, int(dtype), int(mode)))
 
     def selector_info(self, dtype=F32):
         kind, k, fb = c_i32(), c_i32(), c_i32()
@@ -795,13 +797,14 @@ class Handle:
     @staticmethod
     def _opts_tuple(o):
         return (o.config_id, o.small_config_id, int(o.small_max_area), o.schedule, o.order,
-                o.wgs_per_cu)
+                o.wgs_per_cu, o.pipeline)
 
     def grouped_plan(self, shapes, A, B, C, alpha=1.0, beta=0.0, opts=None, workspace=None,
                      ws_bytes=0, dtype=BF16, stream=None, ld=None):
         """shapes: list of (M, N, K); A, B, C: lists of device buffers; ld:
         None or per member (lda, ldb, ldc); opts: GroupedOpts or (config_id,
-        small_config_id, small_max_area, schedule, order, wgs_per_cu[, visits])."""
+        small_config_id, small_max_area, schedule, order, wgs_per_cu[, pipeline[,
+        visits]])."""
         arr = shapes_array([(m, n, k, 1, 0, 0) for (m, n, k) in shapes])
         plan = c_vp()
         o = None

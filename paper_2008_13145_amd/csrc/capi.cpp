@@ -136,7 +136,7 @@ using namespace kt;
 
 extern "C" {
 
-int32_t kt_abi_version(void) { return 110; }
+int32_t kt_abi_version(void) { return 111; }
 
 kt_status kt_create(kt_handle* out, int device) {
   if (!out) return fail(nullptr, KT_EINVAL, "out is NULL");

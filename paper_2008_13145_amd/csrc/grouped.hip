@@ -215,7 +215,8 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
   const GroupedVariant* v = variant_for(h, o.config_id, o.small_config_id);
   if (!v) return fail(h, KT_EUNSUPPORTED, "BF16 tile pair not compiled for the grouped kernel");
   if (o.small_max_area < 0) return fail(h, KT_EINVAL, "negative small-member area");
-  if (o.schedule < 0 || o.schedule > 1 || o.order < 0 || o.order > 1 || o.wgs_per_cu < 1 || o.wgs_per_cu > 4)
+  if (o.schedule < 0 || o.schedule > 1 || o.order < 0 || o.order > 1 || o.wgs_per_cu < 1 ||
+      o.wgs_per_cu > 4 || o.pipeline < 0 || o.pipeline > 1)
     return fail(h, KT_EINVAL, "bad grouped options");
   const size_t need = a256((size_t)n * sizeof(GroupDesc)) + a256((size_t)max_work_items(shapes, n) * sizeof(WorkItem)) + 256;
   if (!ws || ws_bytes < need) return fail(h, KT_EWORKSPACE, "grouped workspace too small");
@@ -230,7 +231,8 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
     d.ldc = ld ? ld[3 * i + 2] : std::max<int64_t>(s.N, 1);
     d.vecA = member_vec(A[i], d.lda);
     d.vecB = member_vec(B[i], d.ldb);
-    d.dma = s.K > 0 && member_dma(A[i], d.lda, s.K) && member_dma(B[i], d.ldb, s.N);
+    d.dma = o.pipeline == 0 && s.K > 0 && member_dma(A[i], d.lda, s.K) &&
+            member_dma(B[i], d.ldb, s.N);
     d.pad = 0;
   }
   std::vector<int32_t> gorder(n);
@@ -397,6 +399,14 @@ kt_status kt_autotune_grouped(kt_handle hh, kt_dtype dtype, const kt_shape* shap
   hipStream_t st = (hipStream_t)stream;
   std::vector<kt_grouped_opts> cands;
   static const int64_t kAreas[] = {0, 128 * 128, 256 * 256, 512 * 512};
+  // register-staged only, and (where some member allows it) the DMA pipeline
+  bool any_dma = false;
+  for (int32_t i = 0; i < n && !any_dma; ++i) {
+    const int64_t lda = ld ? ld[3 * i] : std::max<int64_t>(shapes[i].K, 1);
+    const int64_t ldb = ld ? ld[3 * i + 1] : std::max<int64_t>(shapes[i].N, 1);
+    any_dma = shapes[i].K > 0 && member_dma(A[i], lda, shapes[i].K) &&
+              member_dma(B[i], ldb, shapes[i].N);
+  }
   for (int vi = 0; vi < kNumVariants; ++vi) {
     const GroupedVariant& v = kGroupedVariants[vi];
     const int32_t big = config_id_of(h, v.bm, v.bn, v.t, v.bk);
@@ -405,15 +415,17 @@ kt_status kt_autotune_grouped(kt_handle hh, kt_dtype dtype, const kt_shape* shap
     for (int64_t area : kAreas)
       for (int sched = 0; sched < 2; ++sched)
         for (int order = 0; order < 2; ++order)
-          for (int wgs = 1; wgs <= 2; ++wgs) {
-            kt_grouped_opts o;
-            memset(&o, 0, sizeof o);
-            o.config_id = big;
-            o.small_config_id = area > 0 ? small : -1;
-            o.small_max_area = area;
-            o.schedule = sched; o.order = order; o.wgs_per_cu = wgs;
-            cands.push_back(o);
-          }
+          for (int wgs = 1; wgs <= 2; ++wgs)
+            for (int pipe = any_dma ? 0 : 1; pipe < 2; ++pipe) {
+              kt_grouped_opts o;
+              memset(&o, 0, sizeof o);
+              o.config_id = big;
+              o.small_config_id = area > 0 ? small : -1;
+              o.small_max_area = area;
+              o.schedule = sched; o.order = order; o.wgs_per_cu = wgs;
+              o.pipeline = pipe;
+              cands.push_back(o);
+            }
   }
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);

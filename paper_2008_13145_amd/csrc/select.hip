@@ -368,7 +368,7 @@ kt_status select_config(Ctx* h, int dtype, const kt_shape* s, int32_t* id) {
   // allocate, where the model's pick stands).
   if (S.kind >= KT_SEL_DT_A && S.kind <= KT_SEL_MLP && S.fallback && S.have_box &&
       outside_box(S, *s) && !h->forbid_alloc && h->device >= 0)
-    return fallback_select(h, dtype, s, id);
+    return S.fallback == 2 ? exhaustive_select(h, dtype, s, id) : fallback_select(h, dtype, s, id);
   return model_select(h, dtype, s, id);
 }
 
@@ -604,7 +604,7 @@ kt_status kt_load(kt_handle hh, const char* path) {
     }
     if (ver >= 3) {
       if (!(in >> tag >> L.have_box >> L.fallback) || tag != "box" || (L.have_box & ~1) ||
-          (L.fallback & ~1))
+          L.fallback < 0 || L.fallback > 2)
         return bad("box");
       for (int q = 0; q < 4; ++q) if (!(in >> L.lo[q])) return bad("box bounds");
       for (int q = 0; q < 4; ++q) if (!(in >> L.hi[q])) return bad("box bounds");
@@ -638,7 +638,7 @@ kt_status kt_set_fallback(kt_handle hh, kt_dtype dtype, int32_t enabled) {
   Ctx* h = reinterpret_cast<Ctx*>(hh);
   if (!h) return fail(nullptr, KT_EINVAL, "NULL handle");
   if (bad_dtype(dtype)) return fail(h, KT_EINVAL, "bad dtype");
-  if (enabled != 0 && enabled != 1) return fail(h, KT_EINVAL, "enabled must be 0 or 1");
+  if (enabled < 0 || enabled > 2) return fail(h, KT_EINVAL, "fallback mode must be 0, 1 or 2");
   h->sel[dtype].fallback = enabled;
   return KT_OK;
 }

@@ -96,7 +96,7 @@ def test_every_option_is_correct_and_covers_each_tile_once(gpu):
                 area = 128 * 128 if order else 0
                 plan = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
                                       opts=kt.GroupedOpts(cid, small if area else -1, area, sched,
-                                                          order, 2, visits.data_ptr()),
+                                                          order, 2, 0, visits.data_ptr()),
                                       workspace=ws, ws_bytes=ws_bytes)
                 n_work, _ = h.grouped_info(plan)
                 h.grouped_launch(plan)
@@ -139,7 +139,7 @@ def test_graph_replays_match_first_run(gpu):
     cid = h.configs(kt.BF16).index((128, 128, 8, 32))
     small = h.configs(kt.BF16).index((64, 64, 4, 32))
     plan = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
-                          opts=kt.GroupedOpts(cid, small, 256 * 256, 1, 1, 2, None),
+                          opts=kt.GroupedOpts(cid, small, 256 * 256, 1, 1, 2, 0, None),
                           workspace=ws, ws_bytes=ws_bytes)
     h.grouped_launch(plan)
     torch.cuda.synchronize()
@@ -207,7 +207,9 @@ def test_rejects_unsupported_members(gpu):
 def test_padded_members_take_the_dma_pipeline(gpu, pair):
     """Members whose rows are padded to 16 bytes (padding full of NaNs) run
     through LDS DMA, reading each row up to its 16-byte boundary: results
-    equal the dense-row (register-staged) plan bit for bit and the oracle."""
+    equal the dense-row (register-staged) plan bit for bit and the oracle;
+    the same padded members forced onto the register-staged pipeline
+    (pipeline 1) give the same bits."""
     import paper_2008_13145_amd as kt
     h, torch = gpu
     shapes = _small_shapes()[:24] + [(5, 3, 7), (64, 64, 8), (33, 17, 9)]
@@ -217,12 +219,14 @@ def test_padded_members_take_the_dma_pipeline(gpu, pair):
     big, small = cfgs.index(pair[0]), cfgs.index(pair[1])
     ws_bytes = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for m, n, k in shapes])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    for area in (0, 256 * 256):
-        opts = kt.GroupedOpts(big, small if area else -1, area, 1, 1, 2, None)
+    for area, pipe in ((0, 0), (256 * 256, 0), (256 * 256, 1)):
+        opts = kt.GroupedOpts(big, small if area else -1, area, 1, 1, 2, 0, None)
         for c in C + C2:
             c.fill_(float("nan"))
-        p1 = h.grouped_plan(shapes, A, B, C, 1.0, 0.0, opts=opts, workspace=ws, ws_bytes=ws_bytes,
-                            ld=ld)
+        p1 = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
+                            opts=kt.GroupedOpts(big, small if area else -1, area, 1, 1, 2, pipe,
+                                                None),
+                            workspace=ws, ws_bytes=ws_bytes, ld=ld)
         h.grouped_launch(p1)
         torch.cuda.synchronize()
         h.grouped_destroy(p1)
@@ -233,7 +237,7 @@ def test_padded_members_take_the_dma_pipeline(gpu, pair):
         h.grouped_destroy(p2)
         for (M, N, K), (sa, sb), x, y in zip(shapes, host, C, C2):
             gx, gy = x.cpu().numpy(), y.cpu().numpy()
-            assert np.array_equal(gx.view(np.uint32), gy.view(np.uint32)), (M, N, K, area)
+            assert np.array_equal(gx.view(np.uint32), gy.view(np.uint32)), (M, N, K, area, pipe)
             if M and N and K:
                 _check_member(M, N, K, sa, sb, gx)
 

@@ -92,7 +92,7 @@ def test_create_rejects_bad_device(kt):
 
 
 def test_abi_version(kt):
-    assert kt.lib().kt_abi_version() == 110
+    assert kt.lib().kt_abi_version() == 111
 
 
 def test_kernel_ids(kt):

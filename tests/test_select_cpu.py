@@ -89,9 +89,11 @@ def test_training_box_saved_and_version_2_files(kt, tmp_path):
     assert info["kind"] == 1 and info["chosen"] == [0, 4, 7] and info["fallback"] == 1
     assert info["box_lo"] == S[:, :4].min(axis=0).tolist()
     assert info["box_hi"] == S[:, :4].max(axis=0).tolist()
-    h.set_fallback(0)
+    with pytest.raises(kt.KtError):
+        h.set_fallback(3)
+    h.set_fallback(2)
     h.fit_selector(2, shapes, T, [0, 4, 7])        # the setting survives a refit
-    assert h.selector_info()["fallback"] == 0
+    assert h.selector_info()["fallback"] == 2
     p = str(tmp_path / "sel.txt")
     h.save(p)
     h2 = kt.Handle(-1)

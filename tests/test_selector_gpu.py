@@ -71,6 +71,14 @@ def test_fallback_times_the_chosen_kernels_outside_the_box(gpu, kt):
     h.set_fallback(1)
     assert h.select(*inside) == p0           # inside the box the model decides
     assert model_pick in CHOSEN8
+    # exhaustive fallback: any kernel the library holds, timed once, cached;
+    # inside the box the model still decides
+    h.set_fallback(2)
+    ex = h.select(*out)
+    assert 0 <= ex < h.num_kernels()
+    assert h.select(*out) == ex
+    assert h.select(*inside) == p0
+    h.set_fallback(1)
 
 
 def test_validated_selector_scores_match_the_oracle(gpu, kt):
