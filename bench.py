@@ -938,6 +938,11 @@ def main(argv=None):
     h = kt.Handle(0)
     kernels = h.kernels()
     assert [tuple(c) for c in C.tolist()] == kernels[:n_cfg], "table columns are not this build's kernels"
+    # the operand layout the table was measured with: rows padded to 16
+    # elements (allocated in full, promised to the library) or dense; the
+    # fallback's timings below use it too
+    pad = bool(meta.get("pad_rows", False))
+    h.set_full_rows(pad)
     # partial planes for the split-K kernels kt_gemm runs (selected or forced)
     gemm_ws = torch.empty(kt.SPLIT_PLANE_CAP, dtype=torch.uint8, device="cuda")
     h.set_workspace(gemm_ws)
@@ -1131,10 +1136,6 @@ def main(argv=None):
     pool = torch.empty(ws_all // 4 + 64, dtype=torch.float32, device="cuda")
     h.fill_uniform(pool, pool.numel(), synth.operand_seed(synth.SEED, 0), stream=stream)
     base = pool.data_ptr()
-    # the operand layout the table was measured with: rows padded to 16
-    # elements (allocated in full, promised to the library) or dense
-    pad = bool(meta.get("pad_rows", False))
-    h.set_full_rows(pad)
     rnd = (lambda v: (v + 15) // 16 * 16) if pad else (lambda v: v)
     plans = []
     for (M, N, K, b, ta, tb) in problems:
