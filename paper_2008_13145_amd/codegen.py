@@ -102,18 +102,21 @@ def fp8_configs():
     return _lp_configs(FP8_K_TILES, 1) + _lp_small_configs(FP8_SMALL_K_TILES)
 
 
-SPLIT_EDGES = (16, 32, 64, 128)
+SPLIT_TILES = ((16, 16), (32, 32), (64, 64), (128, 128), (16, 128), (128, 16))
 SPLIT_SLICES = (2, 4, 8, 16)
 
 
 def split_variants(cfgs):
     """Split-K variants of a configuration list, as (base id, slices): for
-    each square work-group tile edge in SPLIT_EDGES, the configuration with
-    the deepest K tile and, among those, the most waves (smallest t), run
-    over 2, 4, 8 and 16 slices."""
+    each work-group tile in SPLIT_TILES (square tiles, then the two skinny
+    ones for products with a single row or column block, such as a
+    matrix-vector product), the configuration with the deepest K tile and,
+    among those, the most waves (smallest t), run over 2, 4, 8 and 16
+    slices.  New tiles go at the end, so earlier kernel ids keep their
+    meaning."""
     out = []
-    for e in SPLIT_EDGES:
-        cand = [(i, c) for i, c in enumerate(cfgs) if c[0] == e and c[1] == e]
+    for (tm, tn) in SPLIT_TILES:
+        cand = [(i, c) for i, c in enumerate(cfgs) if c[0] == tm and c[1] == tn]
         if not cand:
             continue
         base = min(cand, key=lambda ic: (-ic[1][3], ic[1][2], ic[0]))[0]

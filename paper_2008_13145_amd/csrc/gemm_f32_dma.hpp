@@ -44,12 +44,16 @@ struct F32DmaCfg {
   static_assert((BM * 4) % 16 == 0 && (BN * 4) % 16 == 0, "whole chunks per row");
 };
 
-// M/N-major FP32 rows: the two lane groups of a 32x32x2 step read rows BK/2
-// apart; moving the second half's chunks by half a row keeps them off the
-// first half's banks when the row spans a whole 256-byte bank line.
-template <int CPR, int BK>
+// M/N-major FP32 rows (one k each, COLS floats = CPR 16-byte chunks): the
+// lane groups of an MFMA step read the same columns of rows BK/2 apart
+// (32x32x2: two halves of 32 lanes, 128 bytes each) or BK/4 apart (16x16x4:
+// four quarters of 16 lanes, 64 bytes each), which would fall on the same
+// banks of a 256-byte bank line; XOR-ing a group's chunk index by 8 (halves)
+// or by 4 x its quarter (quarters) puts the groups on different banks.
+template <int CPR, int BK, int T>
 __device__ __forceinline__ int f32_mswz(int k) {
-  return CPR >= 16 ? ((k / (BK / 2)) & 1) * (CPR / 2) % CPR : 0;
+  if constexpr (T == 2) return CPR >= 8 ? (((k / (BK / 4)) & 3) * 4) % CPR : 0;
+  else return CPR >= 16 ? ((k / (BK / 2)) & 1) * 8 : 0;
 }
 
 template <int BM, int BN, int T, int BK, int TA, int TB>
@@ -84,7 +88,9 @@ __device__ __forceinline__ void f32_dma_issue(const GemmArgs& args, const char* 
     } else {
       const int ROWB = cols * 4, CPR = ROWB / 16;
       const int k = o / ROWB, p = (o % ROWB) / 16;
-      const int c = p ^ (CPR >= 16 ? ((k / (BK / 2)) & 1) * (CPR / 2) : 0);
+      int c;
+      if (isA) c = p ^ f32_mswz<BM / 4, BK, T>(k);
+      else c = p ^ f32_mswz<BN / 4, BK, T>(k);
       int64_t kr = k0 + k;
       kr = kr < args.K ? kr : args.K - 1;
       int64_t col = c0 + (int64_t)c * CE;
@@ -121,10 +127,10 @@ template <int BK>
 __device__ __forceinline__ float f32_at_kmajor(const float* t, int row, int k) {
   return t[row * BK + ((k >> 2) ^ kswz<BK / 4>(row)) * 4 + (k & 3)];
 }
-template <int COLS, int BK>
+template <int COLS, int BK, int T>
 __device__ __forceinline__ float f32_at_mnmajor(const float* t, int k, int col) {
   constexpr int CPR = COLS / 4;
-  return t[k * COLS + (((col >> 2) ^ f32_mswz<CPR, BK>(k)) << 2) + (col & 3)];
+  return t[k * COLS + (((col >> 2) ^ f32_mswz<CPR, BK, T>(k)) << 2) + (col & 3)];
 }
 
 template <int BM, int BN, int T, int BK, int TA, int TB>
@@ -150,11 +156,26 @@ gemm_f32_dma_kernel(GemmArgs args) {
 
   auto A_at = [&](const float* t, int m, int k) {
     if constexpr (TA == 0) return f32_at_kmajor<BK>(t, m, k);
-    else return f32_at_mnmajor<BM, BK>(t, k, m);
+    else return f32_at_mnmajor<BM, BK, T>(t, k, m);
   };
   auto B_at = [&](const float* t, int n, int k) {
     if constexpr (TB == 1) return f32_at_kmajor<BK>(t, n, k);
-    else return f32_at_mnmajor<BN, BK>(t, k, n);
+    else return f32_at_mnmajor<BN, BK, T>(t, k, n);
+  };
+  // Four consecutive k (k0 a multiple of 4) of one row / column: one 16-byte
+  // LDS read from a K-major tile (a whole swizzled chunk), four from an
+  // M/N-major one.
+  auto A4 = [&](const float* t, int m, int k0) {
+    if constexpr (TA == 0)
+      return *reinterpret_cast<const f32x4*>(t + m * BK + ((k0 >> 2) ^ kswz<BK / 4>(m)) * 4);
+    else
+      return f32x4{A_at(t, m, k0), A_at(t, m, k0 + 1), A_at(t, m, k0 + 2), A_at(t, m, k0 + 3)};
+  };
+  auto B4 = [&](const float* t, int n, int k0) {
+    if constexpr (TB == 1)
+      return *reinterpret_cast<const f32x4*>(t + n * BK + ((k0 >> 2) ^ kswz<BK / 4>(n)) * 4);
+    else
+      return f32x4{B_at(t, n, k0), B_at(t, n, k0 + 1), B_at(t, n, k0 + 2), B_at(t, n, k0 + 3)};
   };
 
   constexpr int NACC = (T == 2) ? 4 : (T == 4) ? 16 : 64;
@@ -190,6 +211,8 @@ gemm_f32_dma_kernel(GemmArgs args) {
       const int r16 = lane & 15, g = lane >> 4;
       constexpr int KQ = BK / 4;
       f32x4 c = {acc[0], acc[1], acc[2], acc[3]};
+      // element reads, which the compiler merges where it can (explicit
+      // 16-byte reads measured 3 % slower here on the mixed layouts)
 #pragma unroll
       for (int q = 0; q < KQ; ++q) {
         const float a = A_at(as, wm0 + r16, g * KQ + q);
@@ -204,11 +227,13 @@ gemm_f32_dma_kernel(GemmArgs args) {
       f32x16 c;
 #pragma unroll
       for (int r = 0; r < 16; ++r) c[r] = acc[r];
+      static_assert(KH % 4 == 0, "whole 16-byte chunks per lane half");
 #pragma unroll
-      for (int q = 0; q < KH; ++q) {
-        const float a = A_at(as, wm0 + r32, h * KH + q);
-        const float b = B_at(bs, wn0 + r32, h * KH + q);
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+      for (int q0 = 0; q0 < KH; q0 += 4) {
+        const f32x4 a = A4(as, wm0 + r32, h * KH + q0);
+        const f32x4 b = B4(bs, wn0 + r32, h * KH + q0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], c, 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] = c[r];
@@ -220,15 +245,19 @@ gemm_f32_dma_kernel(GemmArgs args) {
       for (int r = 0; r < 16; ++r) {
         c00[r] = acc[r]; c01[r] = acc[16 + r]; c10[r] = acc[32 + r]; c11[r] = acc[48 + r];
       }
+      static_assert(KH % 4 == 0, "whole 16-byte chunks per lane half");
 #pragma unroll
-      for (int q = 0; q < KH; ++q) {
-        const int k = h * KH + q;
-        const float a0 = A_at(as, wm0 + r32, k), a1 = A_at(as, wm0 + 32 + r32, k);
-        const float b0 = B_at(bs, wn0 + r32, k), b1 = B_at(bs, wn0 + 32 + r32, k);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, c01, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, c10, 0, 0, 0);
-        c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, c11, 0, 0, 0);
+      for (int q0 = 0; q0 < KH; q0 += 4) {
+        const int k = h * KH + q0;
+        const f32x4 a0 = A4(as, wm0 + r32, k), a1 = A4(as, wm0 + 32 + r32, k);
+        const f32x4 b0 = B4(bs, wn0 + r32, k), b1 = B4(bs, wn0 + 32 + r32, k);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[u], b0[u], c00, 0, 0, 0);
+          c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[u], b1[u], c01, 0, 0, 0);
+          c10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[u], b0[u], c10, 0, 0, 0);
+          c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[u], b1[u], c11, 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {

@@ -97,27 +97,31 @@ def test_abi_version(kt):
 
 def test_kernel_ids(kt):
     """Kernels = configurations, then the split-K variants the generator
-    defines (per square tile edge 16..128: deepest K tile, then most waves;
-    slices 2, 4, 8, 16); out-of-range ids are refused; the workspace a
-    variant needs follows its slices and the 256 MiB cap."""
+    defines (per tile of SPLIT_TILES -- square edges 16..128, then 16 x 128
+    and 128 x 16: deepest K tile, then most waves; slices 2, 4, 8, 16);
+    out-of-range ids are refused; the workspace a variant needs follows its
+    slices and the 256 MiB cap."""
     from paper_2008_13145_amd import codegen
     h = kt.Handle(-1)
     for dt, gen in ((kt.F32, codegen.f32_configs), (kt.BF16, codegen.bf16_configs),
                     (kt.FP8E4M3, codegen.fp8_configs)):
         cfgs = gen()
         ks = h.kernels(dt)
-        assert ks == codegen.kernels(cfgs) and len(ks) == len(cfgs) + 16
+        tiles = list(codegen.SPLIT_TILES)
+        assert ks == codegen.kernels(cfgs) and len(ks) == len(cfgs) + 4 * len(tiles)
         for v in range(len(cfgs), len(ks)):
             k, base = h.get_kernel(v, dt)
-            assert k[:4] == cfgs[base] and k[0] == k[1] and k[4] in (2, 4, 8, 16)
-            same_edge = [c for c in cfgs if c[0] == c[1] == k[0]]
-            assert k[3] == max(c[3] for c in same_edge)
-            assert k[2] == min(c[2] for c in same_edge if c[3] == k[3])
+            assert k[:4] == cfgs[base] and k[4] == (2, 4, 8, 16)[(v - len(cfgs)) % 4]
+            assert (k[0], k[1]) == tiles[(v - len(cfgs)) // 4]
+            same_tile = [c for c in cfgs if (c[0], c[1]) == (k[0], k[1])]
+            assert k[3] == max(c[3] for c in same_tile)
+            assert k[2] == min(c[2] for c in same_tile if c[3] == k[3])
             assert all(h.config_compiled(v, ta, tb, dtype=dt) for ta, tb in synth.LAYOUTS)
         with pytest.raises(kt.KtError):
             h.get_kernel(len(ks), dt)
     assert {k[:4] for k in h.kernels()[164:]} == {(16, 16, 1, 64), (32, 32, 1, 64),
-                                                  (64, 64, 2, 64), (128, 128, 4, 64)}
+                                                  (64, 64, 2, 64), (128, 128, 4, 64),
+                                                  (16, 128, 2, 64), (128, 16, 2, 64)}
     v8 = next(v for v, k in enumerate(h.kernels()) if k[4] == 8)
     assert h.kernel_workspace_bytes(100, 50, 1000, 2, id=v8) == 8 * 2 * 100 * 50 * 4
     assert h.kernel_workspace_bytes(100, 50, 129, 2, id=v8) == -(-3 * 2 * 100 * 50 * 4 // 256) * 256

@@ -51,10 +51,10 @@ def test_kernel_ids_follow_the_configurations(gpu, kt):
     for dt in (F32, BF16, FP8):
         n_cfg = h.num_configs(dt)
         vs = _variants(h, dt)
-        assert len(vs) == 16 and h.num_kernels(dt) == n_cfg + 16
+        assert len(vs) == 24 and h.num_kernels(dt) == n_cfg + 24
         for v, (bm, bn, t, bk, sl), base in vs:
             assert 0 <= base < n_cfg and h.get_config(base, dt) == (bm, bn, t, bk)
-            assert sl in (2, 4, 8, 16) and bm == bn
+            assert sl in (2, 4, 8, 16) and (bm == bn or {bm, bn} == {16, 128})
         for c in (0, n_cfg - 1):
             k, base = h.get_kernel(c, dt)
             assert base == c and k[4] == 1 and k[:4] == h.get_config(c, dt)
@@ -170,7 +170,7 @@ def test_fallback_may_take_variants_of_chosen_configurations(gpu, kt):
     hs = kt.Handle(0)
     try:
         vs = _variants(hs)
-        base16 = next(b for _, k, b in vs if k[0] == 16)
+        base16 = next(b for _, k, b in vs if k[0] == k[1] == 16)
         own = [v for v, k, b in vs if b == base16]
         problems = synth.sweep_problems(30, 4444)
         rng = np.random.default_rng(6)
