@@ -1165,13 +1165,15 @@ def main(argv=None):
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in problems] for _ in range(a.steps)]
     torch.cuda.synchronize()
-    state_before = gpu_state()
+    # (not in --step-only runs, which run under the profiler: rocm-smi is a
+    # child process and the profiler's preload would follow it)
+    state_before = None if a.step_only else gpu_state()
     t_start = time.perf_counter()
     for s in range(a.steps):
         step(evs[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    state_after = gpu_state()
+    state_after = None if a.step_only else gpu_state()
     ms_per_step = wall * 1e3 / a.steps
     per_launch = np.array([[evs[s][i][0].elapsed_time(evs[s][i][1]) for i in range(n_prob)]
                            for s in range(a.steps)])          # ms
