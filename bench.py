@@ -485,7 +485,8 @@ def deploy_info(chosen, n_configs):
     if os.path.exists(dep) and os.path.exists(spec_path):
         spec = _json.load(open(spec_path))
         out.update({"deploy_library_bytes": os.path.getsize(dep),
-                    "deploy_kernels": f"{len(spec['chosen'])} FP32 configurations x 4 layouts",
+                    "deploy_kernels": f"{len(spec['chosen'])} FP32 kernels ({len(spec['config_ids'])} "
+                                      "configurations x 4 layouts, split-K variants of them included)",
                     "deploy_choice_matches_this_run": [int(c) for c in spec["chosen"]] == [int(c) for c in chosen]})
     return out
 
