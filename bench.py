@@ -430,31 +430,44 @@ def vgg16_section(kt, h, torch, synth, stream, reps=10, cfg_reps=3):
 
 
 def repeatability(kt, h, torch, T, problems, plans, stream, n_rows=50, rounds=5, seed=13145):
-    """Re-time the best configuration of `n_rows` seeded rows `rounds` times
-    (operands resident, three launches per timing): coefficient of variation
-    per row."""
+    """Re-time the best kernel of `n_rows` seeded rows `rounds` times with the
+    sweep's protocol (operands resident, two warm-up launches, then launches
+    worth about 5 ms per timing, at least 3, at most 200): coefficient of
+    variation of the per-launch time across rounds, and the ratio of the
+    re-timed mean to the table's entry."""
     rng = np.random.default_rng(seed)
     rows = sorted(int(r) for r in rng.choice(len(problems), n_rows, replace=False))
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    cvs = []
+    cvs, ratios = [], []
     for r in rows:
         best = int(np.argmin(T[r]))
         pl = plans[r]
+        t_tab = float(T[r, best]) * 1e-6              # ms
+
+        def launch():
+            h.gemm_raw(kt.F32, pl[0], 1.0, pl[1], pl[2], pl[3], pl[4], pl[5], pl[6], 0.0,
+                       pl[7], pl[8], pl[9], config_id=best, stream=stream)
+        n = int(min(200, max(3, np.ceil(5.0 / max(t_tab, 1e-4)))))
         ts = []
         for _ in range(rounds):
+            for _ in range(2):
+                launch()
             e0.record(stream)
-            for _ in range(3):
-                h.gemm_raw(kt.F32, pl[0], 1.0, pl[1], pl[2], pl[3], pl[4], pl[5], pl[6], 0.0,
-                           pl[7], pl[8], pl[9], config_id=best, stream=stream)
+            for _ in range(n):
+                launch()
             e1.record(stream)
             e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
+            ts.append(e0.elapsed_time(e1) / n)
         ts = np.array(ts)
         cvs.append(float(ts.std() / ts.mean()))
-    cvs = np.array(cvs)
+        ratios.append(float(ts.mean() / t_tab))
+    cvs, ratios = np.array(cvs), np.array(ratios)
     return {"rows": n_rows, "rounds": rounds, "cv_median": round(float(np.median(cvs)), 4),
-            "cv_p90": round(float(np.percentile(cvs, 90)), 4), "cv_max": round(float(cvs.max()), 4)}
+            "cv_p90": round(float(np.percentile(cvs, 90)), 4), "cv_max": round(float(cvs.max()), 4),
+            "retimed_over_table_median": round(float(np.median(ratios)), 4),
+            "retimed_over_table_p10_p90": [round(float(np.percentile(ratios, 10)), 4),
+                                           round(float(np.percentile(ratios, 90)), 4)]}
 
 
 def gpu_state():

@@ -130,9 +130,10 @@ kt_status kt_config_compiled(kt_handle h, kt_dtype dtype, int32_t id, int32_t tr
  * kt_gemm_splitk(splits = slices, config_id = base) does, when its partial
  * planes (S * batch * M * N floats with S the slices really used, at most
  * 256 MiB) fit the workspace it is given; otherwise it runs as the base
- * configuration unsplit.  Variants: for each square work-group tile edge 16,
- * 32, 64 and 128, the configuration with the deepest K tile and then the most
- * waves, over 2, 4, 8 and 16 slices (16 variants per dtype).  A variant
+ * configuration unsplit.  Variants: for each work-group tile 16x16, 32x32,
+ * 64x64, 128x128, 16x128 and 128x16 (in this order), the configuration with
+ * the deepest K tile and then the most waves, over 2, 4, 8 and 16 slices (24
+ * variants per dtype).  A variant
  * needs no code of its own: it is compiled wherever its base is. */
 kt_status kt_num_kernels(kt_handle h, kt_dtype dtype, int32_t* n);
 /* Kernel `id`: its configuration (the base's for a variant), the base
