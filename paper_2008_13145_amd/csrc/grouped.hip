@@ -45,38 +45,42 @@ struct WorkItem {
   int32_t g, tm, tn, cls;   // cls 0: the large tile, 1: the small tile
 };
 
-// One tile class.  WITH_DMA: members whose operands allow it take the DMA
-// pipeline (the kernel then reserves its LDS); without, every member is
-// register-staged and the kernel keeps the smaller LDS footprint (more
-// resident work-groups) -- the plan picks the variant by its members.
-template <int BM, int BN, int T, int BK, bool WITH_DMA>
+// One tile class.  MODE 0: every member register-staged (the smaller LDS
+// footprint keeps more work-groups resident); 1: every member through LDS
+// DMA; 2: each member by its own operands (both pipelines compiled into the
+// kernel).  The plan picks the mode from its members, and a kernel holds the
+// small tile class only when the plan uses it: every tile body compiled into
+// the persistent loop keeps its lane-invariant addresses live across the
+// whole loop, and with four bodies the kernels ran out of registers.
+template <int BM, int BN, int T, int BK, int MODE>
 struct GroupTile {
   static constexpr int NT = BM * BN / (T * T);
-  static constexpr int L1 = GemmLpCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES;
-  static constexpr int L2 = WITH_DMA ? LpDmaCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES : 0;
+  static constexpr int L1 = MODE != 1 ? GemmLpCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES : 0;
+  static constexpr int L2 = MODE != 0 ? LpDmaCfg<2, BM, BN, T, BK, 0, 0>::LDS_BYTES : 0;
   static constexpr int LDS = L1 > L2 ? L1 : L2;
 
   __device__ __forceinline__ static void run(const GemmArgs& a, int tm, int tn, bool dma,
                                              char* lds) {
-    if constexpr (WITH_DMA) {
-      if (dma) {
-        lp_dma_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, lds);
-        return;
-      }
+    if constexpr (MODE == 1) {
+      lp_dma_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, lds);
+    } else if constexpr (MODE == 2) {
+      if (dma) lp_dma_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, lds);
+      else lp_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, reinterpret_cast<uint16_t*>(lds));
+    } else {
+      lp_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, reinterpret_cast<uint16_t*>(lds));
     }
-    lp_tile<2, BM, BN, T, BK, 0, 0>(a, tm, tn, 0, reinterpret_cast<uint16_t*>(lds));
   }
 };
 
-template <int BM, int BN, int T, int BK, int SM, int SN, int ST, int SK, bool WITH_DMA>
+template <int BM, int BN, int T, int BK, int SM, int SN, int ST, int SK, int MODE, bool TWO>
 __global__ void __launch_bounds__(BM * BN / (T * T))
 grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restrict__ work,
                     int32_t n_work, float alpha, float beta, int32_t dynamic,
                     uint32_t* __restrict__ counter, uint32_t* __restrict__ visits) {
-  using Big = GroupTile<BM, BN, T, BK, WITH_DMA>;
-  using Small = GroupTile<SM, SN, ST, SK, WITH_DMA>;
+  using Big = GroupTile<BM, BN, T, BK, MODE>;
+  using Small = GroupTile<SM, SN, ST, SK, MODE>;
   static_assert(Big::NT == Small::NT, "both tiles of a grouped kernel have the same waves");
-  constexpr int LDS = Big::LDS > Small::LDS ? Big::LDS : Small::LDS;
+  constexpr int LDS = (!TWO || Big::LDS > Small::LDS) ? Big::LDS : Small::LDS;
   __shared__ __attribute__((aligned(16))) char lds[LDS];
   __shared__ int32_t s_w;
   int32_t w = blockIdx.x;
@@ -98,8 +102,12 @@ grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restr
     a.scaleA = nullptr; a.scaleB = nullptr;
     a.vecA = d.vecA; a.vecB = d.vecB;
     a.tiles_m = 0; a.tiles_n = 0;
-    if (it.cls == 0) Big::run(a, it.tm, it.tn, d.dma != 0, lds);
-    else Small::run(a, it.tm, it.tn, d.dma != 0, lds);
+    if constexpr (TWO) {
+      if (it.cls == 0) Big::run(a, it.tm, it.tn, d.dma != 0, lds);
+      else Small::run(a, it.tm, it.tn, d.dma != 0, lds);
+    } else {
+      Big::run(a, it.tm, it.tn, d.dma != 0, lds);
+    }
     if (visits && threadIdx.x == 0) atomicAdd(&visits[w], 1u);
     __syncthreads();   // LDS and s_w are reused by the next item
     if (!dynamic) w += gridDim.x;
@@ -114,13 +122,14 @@ typedef void (*GroupedKernel)(const GroupDesc*, const WorkItem*, int32_t, float,
 struct GroupedVariant {
   int bm, bn, t, bk;       // large tile
   int sm, sn, st, sk;      // small tile (same waves)
-  GroupedKernel fn_reg;    // every member register-staged
-  GroupedKernel fn_dma;    // members with 16-byte rows through LDS DMA
+  GroupedKernel fn[3][2];  // [mode: register / DMA / per member][small tile class compiled in]
 };
 
-#define KT_GV(a, b, c, d, e, f, g, h)                                            \
-  {a, b, c, d, e, f, g, h, grouped_bf16_kernel<a, b, c, d, e, f, g, h, false>, \
-   grouped_bf16_kernel<a, b, c, d, e, f, g, h, true>}
+#define KT_GK(a, b, c, d, e, f, g, h, m) \
+  {grouped_bf16_kernel<a, b, c, d, e, f, g, h, m, false>, grouped_bf16_kernel<a, b, c, d, e, f, g, h, m, true>}
+#define KT_GV(a, b, c, d, e, f, g, h) \
+  {a, b, c, d, e, f, g, h, {KT_GK(a, b, c, d, e, f, g, h, 0), KT_GK(a, b, c, d, e, f, g, h, 1), \
+                            KT_GK(a, b, c, d, e, f, g, h, 2)}}
 // Tile pairs the grouped kernel is compiled for (members of the BF16
 // configuration space).
 static const GroupedVariant kGroupedVariants[] = {
@@ -132,6 +141,7 @@ static const GroupedVariant kGroupedVariants[] = {
     KT_GV(64, 64, 4, 64, 32, 32, 2, 64),
 };
 #undef KT_GV
+#undef KT_GK
 static constexpr int kNumVariants = sizeof(kGroupedVariants) / sizeof(kGroupedVariants[0]);
 
 static int32_t config_id_of(Ctx* h, int bm, int bn, int t, int bk) {
@@ -273,9 +283,17 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess && n_work > 0) {
     if (o.schedule == 1) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, cs, d_counter);
-    bool any_dma = false;
-    for (const GroupDesc& d : descs) any_dma = any_dma || d.dma;
-    hipLaunchKernelGGL(any_dma ? v->fn_dma : v->fn_reg, dim3(grid), dim3(threads), 0, cs,
+    // register-staged only, DMA only (every member with work allows it; a
+    // member with K = 0 has nothing to load), or per member
+    bool any_dma = false, all_dma = true, two = false;
+    for (int32_t i = 0; i < n; ++i) {
+      if (shapes[i].M == 0 || shapes[i].N == 0) continue;
+      any_dma = any_dma || descs[i].dma;
+      all_dma = all_dma && (descs[i].dma || shapes[i].K == 0);
+    }
+    for (const WorkItem& it : work) two = two || it.cls == 1;
+    const int mode = !any_dma ? 0 : (all_dma ? 1 : 2);
+    hipLaunchKernelGGL(v->fn[mode][two ? 1 : 0], dim3(grid), dim3(threads), 0, cs,
                        (const GroupDesc*)d_desc,
                        (const WorkItem*)d_work, n_work, alpha, beta, (int32_t)o.schedule, d_counter,
                        o.visits);
