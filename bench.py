@@ -909,11 +909,23 @@ def main(argv=None):
     ap.add_argument("--step-only", action="store_true",
                     help="only pruning, the deployed selector and the timed steps (for counter "
                          "runs: the dominant kernel's last dispatches are the timed step's)")
+    ap.add_argument("--grouped-only", action="store_true",
+                    help="only the grouped BF16 section (for profiling its kernel)")
     ap.add_argument("--square-only", action="store_true",
                     help="only the BF16 / FP8 4096^3 section (for profiling its kernels)")
     a = ap.parse_args(argv)
     if a.calibrate_counters:
         calibrate_counters()
+        return 0
+    if a.grouped_only:
+        import torch
+
+        import paper_2008_13145_amd as kt
+        import synth
+        h = kt.Handle(0)
+        print(json.dumps(grouped_section(kt, h, torch, synth, torch.cuda.current_stream())),
+              flush=True)
+        h.close()
         return 0
     if a.square_only:
         import torch
