@@ -48,6 +48,20 @@ __device__ __forceinline__ void vm_wait_barrier() {
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
+// One lane's 16 bytes of a wave's 1 KiB LDS DMA: global `src` to the LDS
+// block at `dst` (wave-uniform; lane l's bytes land at dst + 16 l).  Written
+// as inline asm so the compiler does not track it: its waitcnt pass cannot
+// tell which stage buffer a transpose read touches and otherwise waits for
+// every DMA in flight -- the next stage's included -- before each stage's
+// fragment reads.  Every wait on these transfers is the explicit one of the
+// stage pipeline (vm_wait_barrier); vector-memory operations complete in
+// issue order, so the compiler's own vmcnt waits stay correct.
+__device__ __forceinline__ void lds_dma16(const void* src, void* dst) {
+  const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)(lds_void_t*)dst);
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(m0) : "memory");
+}
+
 template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
 struct LpDmaCfg {
   using Base = GemmLpCfg<EB, BM, BN, T, BK, TA, TB>;
@@ -143,7 +157,7 @@ __device__ __forceinline__ void lp_dma_issue(const GemmArgs& args, const char* _
       elem = kr * ld + col;
     }
     char* dst = stage + (isA ? 0 : Cfg::A_BYTES) + blk * 1024;
-    __builtin_amdgcn_global_load_lds((gbl_void_t*)(base + elem * EB), (lds_void_t*)dst, 16, 0, 0);
+    lds_dma16(base + elem * EB, dst);
   }
 }
 
