@@ -59,7 +59,7 @@ __device__ __forceinline__ void vm_wait_barrier() {
 __device__ __forceinline__ void lds_dma16(const void* src, void* dst) {
   const uint32_t m0 = __builtin_amdgcn_readfirstlane(
       (uint32_t)(uintptr_t)(lds_void_t*)dst);
-  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(m0) : "memory");
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(m0));
 }
 
 template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
@@ -77,6 +77,11 @@ struct LpDmaCfg {
   static constexpr int NBA = A_BYTES / 1024, NBB = B_BYTES / 1024;   // 1 KiB DMA blocks
   static constexpr int NBLK = NBA + NBB;
   static constexpr int NW_LO = NBLK / WAVES, NW_HI = (NBLK + WAVES - 1) / WAVES;
+  // Occupancy target: the waves per SIMD that the LDS footprint allows,
+  // capped at 2, so the register budget (512 / waves) keeps a second
+  // work-group resident wherever the LDS has room for it.
+  static constexpr int OCC_LDS = (160 * 1024 / LDS_BYTES) * WAVES / 4;
+  static constexpr int OCC = OCC_LDS < 1 ? 1 : (OCC_LDS > 2 ? 2 : OCC_LDS);
   static_assert(A_BYTES % 1024 == 0 && B_BYTES % 1024 == 0, "tiles of whole 1 KiB blocks");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
   static_assert((NS - 2) * NW_HI < 64, "vmcnt range");
@@ -346,6 +351,7 @@ __device__ __forceinline__ void lp_dma_tile(const GemmArgs& args, int tm, int tn
 
 template <int EB, int BM, int BN, int T, int BK, int TA, int TB>
 __global__ void __launch_bounds__(BM * BN / (T * T))
+__attribute__((amdgpu_waves_per_eu(LpDmaCfg<EB, BM, BN, T, BK, TA, TB>::OCC, 8)))
 gemm_lp_dma_kernel(GemmArgs args) {
   using Cfg = LpDmaCfg<EB, BM, BN, T, BK, TA, TB>;
   __shared__ __attribute__((aligned(16))) char lds[Cfg::LDS_BYTES];

@@ -72,8 +72,24 @@ struct GroupTile {
   }
 };
 
+// Occupancy target of the DMA-only kernels with one tile class: the waves
+// per SIMD that the LDS allows, capped at 2, so a second work-group stays
+// resident wherever the LDS has room for it (these kernels fit that register
+// budget without spilling; the others do not and keep the compiler's choice).
+template <int LDS, int NT, int MODE, bool TWO>
+struct GroupOcc {
+  static constexpr int RAW = (160 * 1024 / LDS) * (NT / 64) / 4;
+  static constexpr int V = (MODE != 1 || TWO) ? 1 : (RAW < 1 ? 1 : (RAW > 2 ? 2 : RAW));
+};
+
 template <int BM, int BN, int T, int BK, int SM, int SN, int ST, int SK, int MODE, bool TWO>
 __global__ void __launch_bounds__(BM * BN / (T * T))
+__attribute__((amdgpu_waves_per_eu(
+    GroupOcc<(!TWO || GroupTile<BM, BN, T, BK, MODE>::LDS > GroupTile<SM, SN, ST, SK, MODE>::LDS)
+                 ? GroupTile<BM, BN, T, BK, MODE>::LDS
+                 : GroupTile<SM, SN, ST, SK, MODE>::LDS,
+             BM * BN / (T * T), MODE, TWO>::V,
+    8)))
 grouped_bf16_kernel(const GroupDesc* __restrict__ descs, const WorkItem* __restrict__ work,
                     int32_t n_work, float alpha, float beta, int32_t dynamic,
                     uint32_t* __restrict__ counter, uint32_t* __restrict__ visits) {
