@@ -207,9 +207,10 @@ def test_rejects_unsupported_members(gpu):
 def test_padded_members_take_the_dma_pipeline(gpu, pair):
     """Members whose rows are padded to 16 bytes (padding full of NaNs) run
     through LDS DMA, reading each row up to its 16-byte boundary: results
-    equal the dense-row (register-staged) plan bit for bit and the oracle;
-    the same padded members forced onto the register-staged pipeline
-    (pipeline 1) give the same bits."""
+    equal the dense-row (register-staged) plan bit for bit and the oracle,
+    under the dynamic and the static schedule (every item visited once); the
+    same padded members forced onto the register-staged pipeline (pipeline 1)
+    give the same bits."""
     import paper_2008_13145_amd as kt
     h, torch = gpu
     shapes = _small_shapes()[:24] + [(5, 3, 7), (64, 64, 8), (33, 17, 9)]
@@ -219,17 +220,21 @@ def test_padded_members_take_the_dma_pipeline(gpu, pair):
     big, small = cfgs.index(pair[0]), cfgs.index(pair[1])
     ws_bytes = kt.Handle.grouped_workspace_bytes([(m, n, k, 1, 0, 0) for m, n, k in shapes])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    for area, pipe in ((0, 0), (256 * 256, 0), (256 * 256, 1)):
+    for area, pipe, sched in ((0, 0, 0), (0, 0, 1), (256 * 256, 0, 1), (256 * 256, 1, 1)):
         opts = kt.GroupedOpts(big, small if area else -1, area, 1, 1, 2, 0, None)
         for c in C + C2:
             c.fill_(float("nan"))
+        visits = torch.zeros(200000, dtype=torch.int32, device="cuda")
         p1 = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
-                            opts=kt.GroupedOpts(big, small if area else -1, area, 1, 1, 2, pipe,
-                                                None),
+                            opts=kt.GroupedOpts(big, small if area else -1, area, sched, 1, 2, pipe,
+                                                visits.data_ptr()),
                             workspace=ws, ws_bytes=ws_bytes, ld=ld)
+        n_work, _ = h.grouped_info(p1)
         h.grouped_launch(p1)
         torch.cuda.synchronize()
         h.grouped_destroy(p1)
+        v = visits.cpu().numpy()
+        assert (v[:n_work] == 1).all() and not v[n_work:].any()
         p2 = h.grouped_plan(shapes, A2, B2, C2, 1.0, 0.0, opts=opts, workspace=ws,
                             ws_bytes=ws_bytes)
         h.grouped_launch(p2)
