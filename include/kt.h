@@ -657,7 +657,10 @@ typedef struct {
   int32_t small_config_id;  /* BF16 tile of members with M * N <= small_max_area; -1 = none */
   int64_t small_max_area;
   int32_t schedule;         /* 0: static round robin over work-groups; 1: atomic work counter */
-  int32_t order;            /* 0: members in the given order; 1: largest K first */
+  int32_t order;            /* bit 0: members largest K first (else as given); bit 1: each
+                               member's tiles in XCD blocks (its tile grid cut into 8
+                               rectangles, interleaved so round-robin dispatch gives each XCD
+                               one rectangle), else row by row */
   int32_t wgs_per_cu;       /* persistent work-groups per compute unit (1..4) */
   int32_t pipeline;         /* 0: members that allow it take the LDS-DMA pipeline (the kernel
                                then reserves its LDS); 1: every member register-staged (the

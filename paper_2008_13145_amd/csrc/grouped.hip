@@ -234,6 +234,40 @@ static bool member_dma(const void* p, int64_t ld, int64_t ext) {
   return (uintptr_t)p % 16 == 0 && ld % 8 == 0 && ext >= 8 && ld >= (ext + 7) / 8 * 8;
 }
 
+// XCD-blocked tile order of one member: its tile grid cut into 8 rectangles
+// (r rows x c columns of blocks, r c = 8, the blocks as square as the grid
+// allows), emitted interleaved -- block x's j-th tile at position 8 j + x of
+// the member's run -- so that round-robin dispatch over the 8 XCDs gives each
+// XCD one rectangle and its L2 serves the A and B panels the rectangle's
+// tiles share.  False (nothing emitted) for grids too small to cut.
+static bool blocked_tiles(int32_t g, int tmn, int tnn, int cls, std::vector<WorkItem>& work) {
+  int best_r = 0;
+  double best = 0.0;
+  for (int r = 1; r <= 8; r *= 2) {
+    const int c = 8 / r;
+    if (tmn < r || tnn < c) continue;
+    const double bh = (double)tmn / r, bw = (double)tnn / c;
+    const double score = std::min(bh, bw) / std::max(bh, bw);
+    if (best_r == 0 || score > best) { best_r = r; best = score; }
+  }
+  if (best_r == 0) return false;
+  const int r = best_r, c = 8 / r;
+  std::vector<std::vector<WorkItem>> blocks(8);
+  for (int bi = 0; bi < r; ++bi)
+    for (int bj = 0; bj < c; ++bj) {
+      std::vector<WorkItem>& b = blocks[bi * c + bj];
+      for (int tm = (int)((int64_t)tmn * bi / r); tm < (int)((int64_t)tmn * (bi + 1) / r); ++tm)
+        for (int tn = (int)((int64_t)tnn * bj / c); tn < (int)((int64_t)tnn * (bj + 1) / c); ++tn)
+          b.push_back(WorkItem{g, tm, tn, cls});
+    }
+  size_t longest = 0;
+  for (const auto& b : blocks) longest = std::max(longest, b.size());
+  for (size_t j = 0; j < longest; ++j)
+    for (const auto& b : blocks)
+      if (j < b.size()) work.push_back(b[j]);
+  return true;
+}
+
 static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const void* const* A,
                             const void* const* B, float* const* C, const int64_t* ld, float alpha,
                             float beta, const kt_grouped_opts& o, void* ws, size_t ws_bytes,
@@ -241,7 +275,7 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
   const GroupedVariant* v = variant_for(h, o.config_id, o.small_config_id);
   if (!v) return fail(h, KT_EUNSUPPORTED, "BF16 tile pair not compiled for the grouped kernel");
   if (o.small_max_area < 0) return fail(h, KT_EINVAL, "negative small-member area");
-  if (o.schedule < 0 || o.schedule > 1 || o.order < 0 || o.order > 1 || o.wgs_per_cu < 1 ||
+  if (o.schedule < 0 || o.schedule > 1 || o.order < 0 || o.order > 3 || o.wgs_per_cu < 1 ||
       o.wgs_per_cu > 4 || o.pipeline < 0 || o.pipeline > 1)
     return fail(h, KT_EINVAL, "bad grouped options");
   const size_t need = a256((size_t)n * sizeof(GroupDesc)) + a256((size_t)max_work_items(shapes, n) * sizeof(WorkItem)) + 256;
@@ -263,7 +297,7 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
   }
   std::vector<int32_t> gorder(n);
   std::iota(gorder.begin(), gorder.end(), 0);
-  if (o.order == 1)   // longest processing time first: tile work grows with K
+  if (o.order & 1)   // longest processing time first: tile work grows with K
     std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) { return shapes[a].K > shapes[b].K; });
   std::vector<WorkItem> work;
   for (int32_t g : gorder) {
@@ -272,6 +306,7 @@ static kt_status plan_build(Ctx* h, const kt_shape* shapes, int32_t n, const voi
     const int cls = (o.small_config_id >= 0 && s.M * s.N <= o.small_max_area) ? 1 : 0;
     const int bm = cls ? v->sm : v->bm, bn = cls ? v->sn : v->bn;
     const int tmn = (int)cdiv(s.M, bm), tnn = (int)cdiv(s.N, bn);
+    if ((o.order & 2) && blocked_tiles(g, tmn, tnn, cls, work)) continue;
     for (int tm = 0; tm < tmn; ++tm)
       for (int tn = 0; tn < tnn; ++tn) work.push_back(WorkItem{g, tm, tn, cls});
   }
@@ -448,7 +483,7 @@ kt_status kt_autotune_grouped(kt_handle hh, kt_dtype dtype, const kt_shape* shap
     if (big < 0 || small < 0) continue;
     for (int64_t area : kAreas)
       for (int sched = 0; sched < 2; ++sched)
-        for (int order = 0; order < 2; ++order)
+        for (int order = 0; order < 4; ++order)
           for (int wgs = 1; wgs <= 2; ++wgs)
             for (int pipe = any_dma ? 0 : 1; pipe < 2; ++pipe) {
               kt_grouped_opts o;

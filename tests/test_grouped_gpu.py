@@ -88,12 +88,13 @@ def test_every_option_is_correct_and_covers_each_tile_once(gpu):
     first = None
     for cid, small in cand_ids:
         for sched in (0, 1):
-            for order in (0, 1):
+            for order in (0, 1, 2, 3):
                 visits = torch.zeros(200000, dtype=torch.int32, device="cuda")
                 for c in C:
                     c.fill_(float("nan"))
-                # order 1 also sends members up to 128 x 128 outputs to the small tile
-                area = 128 * 128 if order else 0
+                # largest-K-first orders also send members up to 128 x 128 outputs to
+                # the small tile
+                area = 128 * 128 if order & 1 else 0
                 plan = h.grouped_plan(shapes, A, B, C, 1.0, 0.0,
                                       opts=kt.GroupedOpts(cid, small if area else -1, area, sched,
                                                           order, 2, 0, visits.data_ptr()),
@@ -113,8 +114,8 @@ def test_every_option_is_correct_and_covers_each_tile_once(gpu):
                             else:
                                 _check_member(M, N, K, sa, sb, got)
                     first = outs
-                elif cid == cand_ids[0][0] and order == 0:
-                    # every schedule computes each tile with the same code
+                elif cid == cand_ids[0][0] and not order & 1:
+                    # every schedule and tile order computes each tile with the same code
                     for x, y in zip(outs, first):
                         assert np.array_equal(x, y, equal_nan=True)
                 else:
