@@ -695,7 +695,7 @@ kt_status kt_grouped_gemm(kt_handle h, kt_dtype dtype, const kt_shape* shapes, i
                           const int64_t* ld, float alpha, float beta, const kt_grouped_opts* opts,
                           void* workspace, size_t ws_bytes, void* stream);
 /* The library's autotuner: successive halving over (tile pair, small-member
- * area in {0, 128^2, 256^2, 512^2}, schedule, order, work-groups per CU,
+ * area in {0, 128^2, 256^2, 512^2}, schedule, order (all four values), work-groups per CU,
  * pipeline -- DMA only when some member allows it),
  * timing whole graph launches of the real group (C is overwritten with
  * alpha = 1, beta = 0).  The winner is returned and kept on the handle as the
