@@ -1,4 +1,4 @@
-"""The deployed selector on the GPU (section 5.1 and the spec learned
+"""The deployed selector on the GPU (section 5.1 and the learned MLP
 selector): host and device MLP picks agree; the out-of-range fallback times
 the chosen kernels; the validated choice of selector scores each kind the
 way the regret oracle does; and, on the committed MI355X timing table, the
