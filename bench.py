@@ -938,8 +938,8 @@ def main(argv=None):
         h.close()
         return 0
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding the "
+              "path over several GPUs is not built", file=sys.stderr)
         return 2
 
     import torch
